@@ -1,0 +1,175 @@
+/*
+ * spin.h -- C ABI of the MI355X (gfx950) library for the checkerboard
+ * Metropolis dynamics of the 2D spin-1/2 Ising and spin-1 Blume-Capel models
+ * (Bisson, Vasilopoulos, Bernaschi, Fatica, Fytas, Gonzalez-Adalid Pemartin,
+ * Martin-Mayor, "Universal exotic dynamics in critical mesoscopic systems",
+ * arXiv:2503.14688).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Lattice: L x L square lattice with periodic boundaries, site (i, j),
+ *   row i, column j (paper, Models: Eq. 1).  L must be a multiple of 64,
+ *   64 <= L <= 2^22.
+ * - Hamiltonian: H = -J sum_<x,y> s_x s_y + Delta sum_x s_x^2 (Eq. 1) with
+ *   J > 0.  Ising: s in {-1, +1} and Delta must be 0.  Blume-Capel: s in
+ *   {-1, 0, +1}, any finite Delta.
+ * - Dynamics: single-spin-flip Metropolis with checkerboard decomposition
+ *   and multispin coding (paper, Introduction).  Colour c = (i + j) & 1;
+ *   one sweep updates colour 0, then colour 1.  Ising proposes s' = -s;
+ *   Blume-Capel proposes one of the two other states with probability 1/2
+ *   each.  Sweeps are counted by t = 0, 1, 2, ...
+ * - Randomness (the paper only says its generator works on 32-bit integers,
+ *   App. A): Philox4x32-10 with key (seed mod 2^32, seed >> 32) and counter
+ *   (i, w, t, purpose << 16 | c << 8 | blk), w = m >> 5 with m = j >> 1.
+ *   Lane b = m & 31 of plane k (k < 32) is bit b of output word k & 3 of the
+ *   block blk = k >> 2; the site's 32-bit uniform u has plane 0 as its most
+ *   significant bit.  purpose 0 = initial state (t = 0), 1 = acceptance,
+ *   2 = Blume-Capel proposal (u >= 2^31 selects s' = -s for s != 0 and
+ *   s' = -1 for s = 0; otherwise s' = 0, respectively +1).
+ * - Acceptance: dE = -J * (double)((s' - s) * h) + Delta * (double)(s'^2 - s^2)
+ *   with h the sum of the four neighbours, evaluated in IEEE double.  A move
+ *   is accepted iff dE <= 0, or 2^32 exp(-dE / T) >= 2^32, or
+ *   u < floor(2^32 exp(-dE / T)) (C library exp, no contraction).
+ * - Initial state (protocol 1, T = infinity start): Ising s = +1 iff
+ *   u < 2^31; Blume-Capel s = floor(3u / 2^32) - 1.
+ *
+ * Device layout (the caller's buffer, spin_lattice_bytes() long):
+ *   Ising:        uint32 P[2][L][L/64]; bit b of P[c][i][w] is 1 iff the
+ *                 spin at (i, j = 2(32w + b) + ((i + c) & 1)) is -1.
+ *   Blume-Capel:  uint32 P[2][L][L/64][2]; word 0 (Z) bit = (s != 0),
+ *                 word 1 (S) bit = (s < 0), S = 0 wherever Z = 0.
+ *
+ * Ownership and threading: the caller owns the device buffer (for instance a
+ * torch uint8 tensor) and every host array; the library never frees them.
+ * The library owns only its handle and small device scratch (reduction
+ * counters, window staging), released by spin_destroy.  Device work is
+ * queued on the handle's HIP stream (NULL = the default stream) and is
+ * asynchronous unless a call says it synchronises.  Calls on one handle are
+ * not reentrant; different handles may be used from different threads.
+ *
+ * Errors: every int-returning call returns 0 on success or a negative
+ * errno-style code: -EINVAL (bad argument), -ENOMEM (host or scratch
+ * allocation), -EIO (a HIP call failed).  spin_last_error() then describes
+ * the failure (thread-local; HIP messages included).  No exception crosses
+ * the ABI.
+ */
+#ifndef SPIN_H
+#define SPIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPIN_ISING 0
+#define SPIN_BLUME_CAPEL 1
+
+/* spin_sweep_ex flag: fuse the energy/magnetisation sums into the colour-1
+ * pass of the last sweep, for the next spin_measure to reuse. */
+#define SPIN_FUSE_MEASURE 1u
+
+/* spin_schedule_fill kinds (paper, Thermal protocols; Table II). */
+#define SPIN_SCHEDULE_CONSTANT 0    /* T(t) = p[0]                              */
+#define SPIN_SCHEDULE_TWO_STEP 1    /* T(t) = p[0] for t < p[1], else p[2]      */
+#define SPIN_SCHEDULE_EXPONENTIAL 2 /* T(t) = p[1] + (p[0] - p[1]) exp(-t/p[2]) */
+
+typedef struct spin_handle spin_handle;
+
+/* Result of spin_measure.  Integer sums are exact; the doubles are derived
+ * from them in IEEE double. */
+typedef struct spin_meas {
+    uint64_t t;      /* sweeps completed when measured                          */
+    int64_t sum_s;   /* sum_x s_x                                               */
+    int64_t sum_s2;  /* sum_x s_x^2                                             */
+    int64_t bond;    /* sum over nearest-neighbour pairs s_x s_y = Sx(1)+Sy(1)  */
+    double e;        /* energy density (-J bond + Delta sum_s2) / L^2, which is
+                        Eq. 3 read with the sign of H (Eq. 1)                   */
+    double m;        /* magnetisation density sum_s / L^2                       */
+    double xi;       /* coherence length I2 / I1 (App. C): trapezoid rule over
+                        r = 0 and the requested r up to r_cut, the last r
+                        before the first C-hat(r) <= 0; 0 if undefined          */
+} spin_meas;
+
+/* Bytes of device memory a lattice needs: L^2 / 8 (Ising, one bit per spin)
+ * or L^2 / 4 (Blume-Capel, two bit planes); paper, Introduction (multispin
+ * coding).  Returns -EINVAL for an unknown model or an unsupported L. */
+int64_t spin_lattice_bytes(int model, uint32_t L);
+
+/* Create a handle over a caller-owned device buffer of at least
+ * spin_lattice_bytes(model, L) bytes, 256-byte aligned.  Does not touch the
+ * buffer's contents; sets t = 0.  hip_stream is a hipStream_t (NULL allowed).
+ * -EINVAL: bad model, L, J <= 0 or not finite, Delta not finite, Ising with
+ * Delta != 0, NULL or short or misaligned buffer. */
+int spin_create(int model, uint32_t L, uint64_t seed, double J, double Delta,
+                void *dev_buf, size_t buf_bytes, void *hip_stream, spin_handle **out);
+
+/* Fill the lattice with the T = infinity start of the thermal protocols
+ * (paper, Thermal protocols).  Asynchronous. */
+int spin_init_random(spin_handle *h);
+
+/* n sweeps; sweep k uses bath temperature T[k] (host array of n doubles) and
+ * stream sweep index t + k, then t += n (paper, Thermal protocols: protocol 1
+ * is a constant T, protocol 2 a time-dependent one).  T[k] must be >= 0 and
+ * not NaN; +inf accepts every move, 0 rejects every dE > 0.  Asynchronous.
+ * sweep(a) followed by sweep(b) equals sweep(a + b) bit for bit.
+ * -EINVAL also when t + n would exceed 2^32 (the counter word holding t). */
+int spin_sweep(spin_handle *h, uint32_t n, const double *T);
+
+/* spin_sweep with flags (SPIN_FUSE_MEASURE).  With n == 0 and the flag set,
+ * only the fused sums of the current state are taken. */
+int spin_sweep_ex(spin_handle *h, uint32_t n, const double *T, uint32_t flags);
+
+/* Measure the current state (paper Eqs. 2-3 and App. C).  Synchronises the
+ * handle's stream.  r: n_r strictly increasing separations, 0 < r < L (host
+ * array).  Sx[q] = sum_{i,j} s(i,j) s(i, j + r_q), Sy[q] = sum_{i,j}
+ * s(i,j) s(i + r_q, j) (periodic, unnormalised), C_hat[q] = (Sx[q] + Sy[q]) /
+ * (2 L^2); each output pointer may be NULL when n_r == 0, C_hat may always be
+ * NULL.  The energy/magnetisation sums come from the fused pass of the
+ * previous spin_sweep_ex when it had SPIN_FUSE_MEASURE and nothing changed
+ * since; otherwise a reduction kernel computes them (same integers). */
+int spin_measure(spin_handle *h, const uint32_t *r, uint32_t n_r, spin_meas *out,
+                 int64_t *Sx, int64_t *Sy, double *C_hat);
+
+/* Copy the whole lattice to host as int8 s[i * L + j].  Synchronises. */
+int spin_get_spins(spin_handle *h, int8_t *host);
+
+/* Copy rows i0 .. i0 + rows - 1 and columns j0 .. j0 + cols - 1 (periodic,
+ * i0, j0 < L, rows, cols <= L) to host as int8 win[a * cols + b].
+ * Synchronises.  Meant for sampled checks of lattices too large for host. */
+int spin_get_window(spin_handle *h, uint32_t i0, uint32_t j0, uint32_t rows, uint32_t cols,
+                    int8_t *host);
+
+/* Overwrite the whole lattice from host int8 s[i * L + j]; -EINVAL if a
+ * value is outside the model's alphabet.  Synchronises. */
+int spin_set_spins(spin_handle *h, const int8_t *host);
+
+/* Set / read the sweep counter t (checkpoint and resume). t < 2^32. */
+int spin_set_t(spin_handle *h, uint64_t t);
+int spin_get_t(const spin_handle *h, uint64_t *t);
+
+/* The library's integer acceptance thresholds for bath temperature T (host
+ * only, no device work).  For Ising, out[0] and out[1] are the thresholds of
+ * dE = 4J and 8J; for Blume-Capel, out[q] for q = 9f + (y + 4) covers move
+ * family f (0: s -> 0 with y = s h, 1: 0 -> s' with y = s' h, 2: s -> -s
+ * with y = s h) and y in [-4, 4].  always[q] is 1 when the move needs no
+ * random number (dE <= 0 or probability 1).  Returns the entry count. */
+int spin_threshold_table(int model, double J, double Delta, double T, uint32_t *out,
+                         uint8_t *always, int capacity);
+
+/* Fill out[k] = T(t0 + k), k < n, for a schedule kind (host FP64). */
+int spin_schedule_fill(int kind, const double *params, uint64_t t0, uint32_t n, double *out);
+
+/* Release the handle and the library's scratch; never the caller's buffer.
+ * Synchronises the stream first. */
+int spin_destroy(spin_handle *h);
+
+/* Thread-local description of the last failure on this thread. */
+const char *spin_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPIN_H */

@@ -1,0 +1,248 @@
+"""Python binding of libspin.so (include/spin.h): argument marshalling only.
+
+Checkerboard Metropolis dynamics of the 2D Ising and spin-1 Blume-Capel
+models (arXiv:2503.14688) on MI355X (gfx950).  Every step of the dynamics,
+the measurements and the derived observables runs inside the native library;
+this module converts arguments, allocates the caller-owned device buffer
+with torch and raises on error codes.  There is no fallback: if libspin.so
+is missing or fails to load, every call raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+ISING = 0
+BLUME_CAPEL = 1
+FUSE_MEASURE = 1
+SCHEDULE_CONSTANT = 0
+SCHEDULE_TWO_STEP = 1
+SCHEDULE_EXPONENTIAL = 2
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspin.so")
+_lib = None
+
+
+class SpinError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class spin_meas(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_uint64), ("sum_s", ctypes.c_int64), ("sum_s2", ctypes.c_int64),
+                ("bond", ctypes.c_int64), ("e", ctypes.c_double), ("m", ctypes.c_double),
+                ("xi", ctypes.c_double)]
+
+
+EXPORTS = ["spin_lattice_bytes", "spin_create", "spin_init_random", "spin_sweep", "spin_sweep_ex",
+           "spin_measure", "spin_get_spins", "spin_get_window", "spin_set_spins", "spin_set_t",
+           "spin_get_t", "spin_threshold_table", "spin_schedule_fill", "spin_destroy",
+           "spin_last_error"]
+
+
+def load_library():
+    """Load libspin.so (built by paper_2503_14688_amd.build); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2503_14688_amd/build.py "
+                          "(no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    f64p = ctypes.POINTER(ctypes.c_double)
+    i8p = ctypes.POINTER(ctypes.c_int8)
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    sig = {
+        "spin_lattice_bytes": (ctypes.c_int64, [ctypes.c_int, ctypes.c_uint32]),
+        "spin_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double,
+                                       ctypes.c_double, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]),
+        "spin_init_random": (ctypes.c_int, [vp]),
+        "spin_sweep": (ctypes.c_int, [vp, ctypes.c_uint32, f64p]),
+        "spin_sweep_ex": (ctypes.c_int, [vp, ctypes.c_uint32, f64p, ctypes.c_uint32]),
+        "spin_measure": (ctypes.c_int, [vp, u32p, ctypes.c_uint32, ctypes.POINTER(spin_meas), i64p, i64p,
+                                        f64p]),
+        "spin_get_spins": (ctypes.c_int, [vp, i8p]),
+        "spin_get_window": (ctypes.c_int, [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                           ctypes.c_uint32, i8p]),
+        "spin_set_spins": (ctypes.c_int, [vp, i8p]),
+        "spin_set_t": (ctypes.c_int, [vp, ctypes.c_uint64]),
+        "spin_get_t": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_uint64)]),
+        "spin_threshold_table": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                                ctypes.c_double, u32p, u8p, ctypes.c_int]),
+        "spin_schedule_fill": (ctypes.c_int, [ctypes.c_int, f64p, ctypes.c_uint64, ctypes.c_uint32,
+                                              f64p]),
+        "spin_destroy": (ctypes.c_int, [vp]),
+        "spin_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _check(rc):
+    if rc < 0:
+        raise SpinError(rc, load_library().spin_last_error().decode())
+    return rc
+
+
+# ---------------------------------------------------------------- C ABI --
+
+def spin_lattice_bytes(model, L):
+    return _check(load_library().spin_lattice_bytes(model, L))
+
+
+def spin_create(model, L, seed, J, Delta, dev_ptr, buf_bytes, hip_stream):
+    h = ctypes.c_void_p()
+    _check(load_library().spin_create(model, L, seed, J, Delta, ctypes.c_void_p(dev_ptr), buf_bytes,
+                                      ctypes.c_void_p(hip_stream), ctypes.byref(h)))
+    return h
+
+
+def spin_init_random(h):
+    _check(load_library().spin_init_random(h))
+
+
+def spin_sweep(h, T):
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    _check(load_library().spin_sweep(h, T.shape[0], _ptr(T, ctypes.c_double)))
+
+
+def spin_sweep_ex(h, T, flags):
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    _check(load_library().spin_sweep_ex(h, T.shape[0], _ptr(T, ctypes.c_double), flags))
+
+
+def spin_measure(h, r=()):
+    """Returns dict(t, sum_s, sum_s2, bond, e, m, xi, Sx, Sy, C_hat)."""
+    r = np.ascontiguousarray(r, dtype=np.uint32)
+    n = r.shape[0]
+    Sx = np.zeros(n, dtype=np.int64)
+    Sy = np.zeros(n, dtype=np.int64)
+    C = np.zeros(n, dtype=np.float64)
+    out = spin_meas()
+    _check(load_library().spin_measure(h, _ptr(r, ctypes.c_uint32), n, ctypes.byref(out),
+                                       _ptr(Sx, ctypes.c_int64), _ptr(Sy, ctypes.c_int64),
+                                       _ptr(C, ctypes.c_double)))
+    return {"t": out.t, "sum_s": out.sum_s, "sum_s2": out.sum_s2, "bond": out.bond, "e": out.e,
+            "m": out.m, "xi": out.xi, "Sx": Sx, "Sy": Sy, "C_hat": C}
+
+
+def spin_get_spins(h, L):
+    s = np.zeros((L, L), dtype=np.int8)
+    _check(load_library().spin_get_spins(h, _ptr(s, ctypes.c_int8)))
+    return s
+
+
+def spin_get_window(h, i0, j0, rows, cols):
+    w = np.zeros((rows, cols), dtype=np.int8)
+    _check(load_library().spin_get_window(h, i0, j0, rows, cols, _ptr(w, ctypes.c_int8)))
+    return w
+
+
+def spin_set_spins(h, s):
+    s = np.ascontiguousarray(s, dtype=np.int8)
+    _check(load_library().spin_set_spins(h, _ptr(s, ctypes.c_int8)))
+
+
+def spin_set_t(h, t):
+    _check(load_library().spin_set_t(h, t))
+
+
+def spin_get_t(h):
+    t = ctypes.c_uint64()
+    _check(load_library().spin_get_t(h, ctypes.byref(t)))
+    return t.value
+
+
+def spin_threshold_table(model, J, Delta, T):
+    out = np.zeros(32, dtype=np.uint32)
+    always = np.zeros(32, dtype=np.uint8)
+    n = _check(load_library().spin_threshold_table(model, J, Delta, T, _ptr(out, ctypes.c_uint32),
+                                                   _ptr(always, ctypes.c_uint8), 32))
+    return out[:n].copy(), always[:n].astype(bool)
+
+
+def spin_schedule_fill(kind, params, t0, n):
+    p = np.zeros(3, dtype=np.float64)
+    p[:len(params)] = params
+    out = np.zeros(n, dtype=np.float64)
+    _check(load_library().spin_schedule_fill(kind, _ptr(p, ctypes.c_double), t0, n,
+                                             _ptr(out, ctypes.c_double)))
+    return out
+
+
+def spin_destroy(h):
+    _check(load_library().spin_destroy(h))
+
+
+def spin_last_error():
+    return load_library().spin_last_error().decode()
+
+
+# ------------------------------------------------- device-buffer holder --
+
+class Lattice:
+    """A lattice whose packed spins live in a torch uint8 tensor on the GPU.
+
+    Holds the tensor (the caller-owned buffer of the C ABI) and the handle;
+    methods forward to the C ABI on the handle's stream.
+    """
+
+    def __init__(self, model, L, seed, J=1.0, Delta=0.0, device="cuda", stream=None):
+        import torch
+        self.model, self.L, self.seed, self.J, self.Delta = model, L, seed, J, Delta
+        nbytes = spin_lattice_bytes(model, L)
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.buf.device)
+        self.h = spin_create(model, L, seed, J, Delta, self.buf.data_ptr(), nbytes,
+                             self.stream.cuda_stream)
+
+    def init_random(self):
+        spin_init_random(self.h)
+        return self
+
+    def sweep(self, T, fuse_measure=False):
+        spin_sweep_ex(self.h, T, FUSE_MEASURE if fuse_measure else 0)
+
+    def measure(self, r=()):
+        return spin_measure(self.h, r)
+
+    def spins(self):
+        return spin_get_spins(self.h, self.L)
+
+    def window(self, i0, j0, rows, cols):
+        return spin_get_window(self.h, i0, j0, rows, cols)
+
+    def set_spins(self, s):
+        spin_set_spins(self.h, s)
+
+    @property
+    def t(self):
+        return spin_get_t(self.h)
+
+    @t.setter
+    def t(self, value):
+        spin_set_t(self.h, value)
+
+    def close(self):
+        if self.h is not None:
+            spin_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

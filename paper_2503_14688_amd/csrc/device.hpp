@@ -1,0 +1,149 @@
+// Device building blocks for gfx950: Philox4x32-10, the lazy bit-plane
+// Metropolis test, bit-sliced counters and block reductions.
+//
+// Every lattice word holds 32 sites of one colour of one row (multispin
+// coding, paper Introduction); all logic below works on 32 sites at once,
+// one bit per site.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spin {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 products, round key bumped by the Weyl constants.
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+struct Block4 {
+    uint32_t v[4];
+};
+
+__device__ __forceinline__ Block4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+    Block4 r;
+    r.v[0] = c0;
+    r.v[1] = c1;
+    r.v[2] = c2;
+    r.v[3] = c3;
+    return r;
+}
+
+// Stream purposes, placed in bits 16.. of counter word 3.
+constexpr uint32_t kPurposeInit = 0u;
+constexpr uint32_t kPurposeAccept = 1u;
+constexpr uint32_t kPurposePropose = 2u;
+
+__device__ __forceinline__ uint32_t stream_tag(uint32_t purpose, uint32_t colour, uint32_t blk)
+{
+    return (purpose << 16) | (colour << 8) | blk;
+}
+
+// Bit-sliced "u < thr" over the 32 sites of a word, evaluated lazily.
+//
+// Site b's uniform u_b is read plane by plane from the most significant bit
+// (plane k = word k & 3 of Philox block k >> 2).  A site is decided at the
+// first plane where its bit differs from its threshold's bit: 0 against 1
+// accepts, 1 against 0 rejects.  Blocks are drawn only while some site of the
+// word is undecided, which gives the same answer as drawing all 32 planes;
+// sites still tied after 32 planes have u == thr and are rejected.
+//
+// need[g]: sites whose move needs a random number and whose threshold is
+// thr[g]; always: sites accepted outright.  Returns the accepted sites.
+template <int NG>
+__device__ __forceinline__ uint32_t metropolis_accept(const uint32_t (&need)[NG], const uint32_t (&thr)[NG],
+                                                      uint32_t always, uint32_t row, uint32_t word,
+                                                      uint32_t t, uint32_t colour, uint32_t k0, uint32_t k1)
+{
+    uint32_t undecided = 0;
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+        undecided |= need[g];
+    uint32_t accepted = always;
+    for (uint32_t blk = 0; blk < 8u && undecided != 0u; ++blk) {
+        const Block4 r = philox4x32_10(row, word, t, stream_tag(kPurposeAccept, colour, blk), k0, k1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t shift = 31u - (4u * blk + (uint32_t)q);
+            uint32_t tb = 0;
+#pragma unroll
+            for (int g = 0; g < NG; ++g)
+                tb |= need[g] & (0u - ((thr[g] >> shift) & 1u));
+            const uint32_t ub = r.v[q];
+            accepted |= undecided & tb & ~ub;
+            undecided &= ~(tb ^ ub);
+        }
+    }
+    return accepted;
+}
+
+// Full adder and half adder on bit-sliced operands.
+__device__ __forceinline__ void full_add(uint32_t a, uint32_t b, uint32_t c, uint32_t &s, uint32_t &carry)
+{
+    const uint32_t x = a ^ b;
+    s = x ^ c;
+    carry = (a & b) | (c & x);
+}
+
+// Bit-sliced count of eight one-bit inputs per site: v = b0 + 2 b1 + 4 b2 + 8 b3.
+__device__ __forceinline__ void count8(const uint32_t (&a)[8], uint32_t &b0, uint32_t &b1, uint32_t &b2,
+                                       uint32_t &b3)
+{
+    uint32_t s1, c1, s2, c2, c4, t1, d1;
+    full_add(a[0], a[1], a[2], s1, c1);
+    full_add(a[3], a[4], a[5], s2, c2);
+    const uint32_t s3 = a[6] ^ a[7];
+    const uint32_t c3 = a[6] & a[7];
+    full_add(s1, s2, s3, b0, c4);
+    full_add(c1, c2, c3, t1, d1);
+    b1 = t1 ^ c4;
+    const uint32_t d2 = t1 & c4;
+    b2 = d1 ^ d2;
+    b3 = d1 & d2;
+}
+
+// 64-bit wave reduction (wave64) followed by one atomic per block.
+template <int N>
+__device__ __forceinline__ void block_reduce_atomic(unsigned long long (&v)[N], unsigned long long *dst)
+{
+    __shared__ unsigned long long part[N][16];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        unsigned long long x = v[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            x += __shfl_xor(x, off, 64);
+        if (lane == 0)
+            part[q][wave] = x;
+    }
+    __syncthreads();
+    const int nwaves = (blockDim.x + 63) >> 6;
+    if (threadIdx.x < N) {
+        unsigned long long s = 0;
+        for (int w = 0; w < nwaves; ++w)
+            s += part[threadIdx.x][w];
+        if (s)
+            atomicAdd(dst + threadIdx.x, s);
+    }
+}
+
+} // namespace spin

@@ -1,0 +1,506 @@
+// gfx950 kernels: initial state, checkerboard half-sweeps (Ising 1 bit per
+// spin, Blume-Capel 2 bit planes), the energy/magnetisation reduction, the
+// axis correlation sums C(r), and the window decoder.
+//
+// Layout (one colour plane per checkerboard colour, paper Introduction):
+// site (i, j) has colour c = (i + j) & 1 and sits at m = j >> 1 of row i of
+// plane c, word w = m >> 5, bit b = m & 31.  Its vertical neighbours are at
+// the same (w, b) in rows i -+ 1 of the other plane; its horizontal
+// neighbours are (i, m) and (i, m - 1) of the other plane when (i + c) is
+// even, (i, m) and (i, m + 1) when it is odd.
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace spin {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kRows = 8;  // rows walked by one thread (vertical register reuse)
+
+inline unsigned grid_for(uint64_t items)
+{
+    uint64_t b = (items + kBlock - 1) / kBlock;
+    if (b > 65536)
+        b = 65536;
+    if (b == 0)
+        b = 1;
+    return (unsigned)b;
+}
+
+// Horizontal neighbour word: bit b holds the site at m -+ 1 of the other
+// plane, built from the same-row word and the word to its left or right.
+__device__ __forceinline__ uint32_t side_word(uint32_t cur, uint32_t nb, uint32_t odd)
+{
+    return odd ? ((cur >> 1) | (nb << 31)) : ((cur << 1) | (nb >> 31));
+}
+
+// ---------------------------------------------------------------- init --
+
+__global__ __launch_bounds__(kBlock) void k_init_ising(uint32_t *planes, uint32_t L, uint32_t W,
+                                                       uint64_t plane_u32, uint32_t k0, uint32_t k1)
+{
+    const uint64_t n = 2 * plane_u32;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t c = g >= plane_u32;
+        const uint64_t rem = g - (c ? plane_u32 : 0);
+        const uint32_t i = (uint32_t)(rem / W);
+        const uint32_t w = (uint32_t)(rem - (uint64_t)i * W);
+        // plane 0 of the stream is the sign bit: u >= 2^31 <=> s = -1
+        planes[g] = philox4x32_10(i, w, 0u, stream_tag(kPurposeInit, c, 0), k0, k1).v[0];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_bc(uint32_t *planes, uint32_t L, uint32_t W,
+                                                    uint64_t plane_u32, uint32_t k0, uint32_t k1)
+{
+    // s = floor(3u / 2^32) - 1: s = -1 iff u < 1431655766, s = 0 iff
+    // 1431655766 <= u < 2863311531, else +1; both comparisons bit-sliced.
+    constexpr uint32_t kThird = 1431655766u, kTwoThirds = 2863311531u;
+    const uint64_t words = plane_u32;  // two uint32 per site word in BC planes
+    const uint64_t n = words;          // (Z, S) pairs over both colours
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t per_plane = plane_u32 / 2;
+        const uint32_t c = g >= per_plane;
+        const uint64_t rem = g - (c ? per_plane : 0);
+        const uint32_t i = (uint32_t)(rem / W);
+        const uint32_t w = (uint32_t)(rem - (uint64_t)i * W);
+        uint32_t lt1 = 0, eq1 = ~0u, lt2 = 0, eq2 = ~0u;
+        for (uint32_t blk = 0; blk < 8; ++blk) {
+            const Block4 r = philox4x32_10(i, w, 0u, stream_tag(kPurposeInit, c, blk), k0, k1);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t sh = 31u - (4u * blk + (uint32_t)q);
+                const uint32_t ub = r.v[q];
+                const uint32_t a = 0u - ((kThird >> sh) & 1u);
+                const uint32_t b = 0u - ((kTwoThirds >> sh) & 1u);
+                lt1 |= eq1 & a & ~ub;
+                eq1 &= ~(a ^ ub);
+                lt2 |= eq2 & b & ~ub;
+                eq2 &= ~(b ^ ub);
+            }
+        }
+        uint2 v;
+        v.x = lt1 | ~lt2;  // nonzero: u < 1/3 or u >= 2/3
+        v.y = lt1;         // negative: u < 1/3
+        reinterpret_cast<uint2 *>(planes)[g] = v;
+    }
+}
+
+// -------------------------------------------------------- Ising sweep --
+
+template <bool MEASURE>
+__global__ __launch_bounds__(kBlock) void k_sweep_ising(Lattice lat, uint32_t c, uint32_t t, GroupTable gt,
+                                                        unsigned long long *acc)
+{
+    const uint32_t L = lat.L, W = lat.W;
+    uint32_t *own = lat.planes + (c ? lat.plane_u32 : 0);
+    const uint32_t *oth = lat.planes + (c ? 0 : lat.plane_u32);
+    const uint64_t nitems = (uint64_t)(L / kRows) * W;
+    const uint32_t thr[2] = {gt.thr[0], gt.thr[1]};
+    const bool rng3 = gt.rng_bits & 1u, rng4 = gt.rng_bits & 2u;
+    const bool nev3 = gt.never_bits & 1u, nev4 = gt.never_bits & 2u;
+    unsigned long long e[kEmCounters] = {0, 0, 0, 0};
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nitems;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t rg = (uint32_t)(g / W);
+        const uint32_t w = (uint32_t)(g - (uint64_t)rg * W);
+        const uint32_t i0 = rg * kRows;
+        const uint32_t wl = (w == 0 ? W : w) - 1u;
+        const uint32_t wr = (w + 1u == W) ? 0u : w + 1u;
+        uint32_t up = oth[(size_t)(i0 == 0 ? L - 1 : i0 - 1) * W + w];
+        uint32_t cur = oth[(size_t)i0 * W + w];
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            const uint32_t i = i0 + (uint32_t)r;
+            const uint32_t inext = (i + 1u == L) ? 0u : i + 1u;
+            const uint32_t dn = oth[(size_t)inext * W + w];
+            const uint32_t odd = (i + c) & 1u;
+            const uint32_t nb = oth[(size_t)i * W + (odd ? wr : wl)];
+            const uint32_t side = side_word(cur, nb, odd);
+            const size_t idx = (size_t)i * W + w;
+            const uint32_t s = own[idx];
+            // aligned-neighbour indicators; a = number aligned, dE = J (4a - 8)
+            const uint32_t e1 = ~(s ^ up), e2 = ~(s ^ dn), e3 = ~(s ^ cur), e4 = ~(s ^ side);
+            const uint32_t a1 = e1 & e2, x1 = e1 ^ e2, a2 = e3 & e4, x2 = e3 ^ e4;
+            const uint32_t m4 = a1 & a2;                // a = 4: dE = 8J
+            const uint32_t m3 = (a1 & x2) | (a2 & x1);  // a = 3: dE = 4J
+            const uint32_t need[2] = {rng3 ? m3 : 0u, rng4 ? m4 : 0u};
+            const uint32_t never = (nev3 ? m3 : 0u) | (nev4 ? m4 : 0u);
+            const uint32_t always = ~(need[0] | need[1] | never);
+            const uint32_t flip = metropolis_accept<2>(need, thr, always, i, w, t, c, lat.key0, lat.key1);
+            const uint32_t ns = s ^ flip;
+            own[idx] = ns;
+            if (MEASURE) {
+                e[0] += 64;
+                e[1] += __popc(ns) + __popc(cur);
+                e[2] += 128;
+                e[3] += __popc(ns ^ up) + __popc(ns ^ dn) + __popc(ns ^ cur) + __popc(ns ^ side);
+            }
+            up = cur;
+            cur = dn;
+        }
+    }
+    if (MEASURE)
+        block_reduce_atomic<kEmCounters>(e, acc);
+}
+
+// -------------------------------------------------- Blume-Capel sweep --
+
+struct Pair {
+    uint32_t z, s;  // z: s != 0, s: s < 0
+};
+
+__device__ __forceinline__ Pair load_pair(const uint32_t *plane, size_t word)
+{
+    const uint2 v = reinterpret_cast<const uint2 *>(plane)[word];
+    return Pair{v.x, v.y};
+}
+
+template <bool MEASURE>
+__global__ __launch_bounds__(kBlock) void k_sweep_bc(Lattice lat, uint32_t c, uint32_t t, GroupTable gt,
+                                                     unsigned long long *acc)
+{
+    const uint32_t L = lat.L, W = lat.W;
+    uint32_t *own = lat.planes + (c ? lat.plane_u32 : 0);
+    const uint32_t *oth = lat.planes + (c ? 0 : lat.plane_u32);
+    const uint64_t nitems = (uint64_t)(L / kRows) * W;
+    uint32_t thr[kBcGroups];
+#pragma unroll
+    for (int g = 0; g < kBcGroups; ++g)
+        thr[g] = gt.thr[g];
+    unsigned long long e[kEmCounters] = {0, 0, 0, 0};
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nitems;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t rg = (uint32_t)(g / W);
+        const uint32_t w = (uint32_t)(g - (uint64_t)rg * W);
+        const uint32_t i0 = rg * kRows;
+        const uint32_t wl = (w == 0 ? W : w) - 1u;
+        const uint32_t wr = (w + 1u == W) ? 0u : w + 1u;
+        Pair up = load_pair(oth, (size_t)(i0 == 0 ? L - 1 : i0 - 1) * W + w);
+        Pair cur = load_pair(oth, (size_t)i0 * W + w);
+#pragma unroll 2
+        for (int r = 0; r < kRows; ++r) {
+            const uint32_t i = i0 + (uint32_t)r;
+            const uint32_t inext = (i + 1u == L) ? 0u : i + 1u;
+            const Pair dn = load_pair(oth, (size_t)inext * W + w);
+            const uint32_t odd = (i + c) & 1u;
+            const Pair nbw = load_pair(oth, (size_t)i * W + (odd ? wr : wl));
+            const Pair side{side_word(cur.z, nbw.z, odd), side_word(cur.s, nbw.s, odd)};
+            const size_t idx = (size_t)i * W + w;
+            const Pair s = load_pair(own, idx);
+            // proposal bit per site: plane 0 of the proposal stream
+            const uint32_t X = philox4x32_10(i, w, t, stream_tag(kPurposePropose, c, 0), lat.key0, lat.key1).v[0];
+            // sign carried by y: that of s when s != 0, of the proposed s' when s = 0
+            const uint32_t neg = (s.z & s.s) | (~s.z & X);
+            const Pair nbr[4] = {up, dn, cur, side};
+            uint32_t bits[8];
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                const uint32_t anti = nbr[n].s ^ neg;
+                bits[n] = nbr[n].z & ~anti;        // neighbour contributes +1 to y
+                bits[4 + n] = ~(nbr[n].z & anti);  // neighbour does not contribute -1
+            }
+            uint32_t b0, b1, b2, b3;
+            count8(bits, b0, b1, b2, b3);  // v = y + 4 in [0, 8]
+            uint32_t Y[9];
+            {
+                const uint32_t nb3 = ~b3;
+                const uint32_t t0 = ~b1 & ~b0, t1 = ~b1 & b0, t2 = b1 & ~b0, t3 = b1 & b0;
+                const uint32_t h0 = nb3 & ~b2, h1 = nb3 & b2;
+                Y[0] = h0 & t0; Y[1] = h0 & t1; Y[2] = h0 & t2; Y[3] = h0 & t3;
+                Y[4] = h1 & t0; Y[5] = h1 & t1; Y[6] = h1 & t2; Y[7] = h1 & t3;
+                Y[8] = b3;
+            }
+            const uint32_t famA = s.z & ~X;  // s -> 0:   dE = J y - Delta
+            const uint32_t famB = ~s.z;      // 0 -> s':  dE = -J y + Delta
+            const uint32_t famC = s.z & X;   // s -> -s:  dE = 2 J y
+            uint32_t need[kBcGroups];
+            uint32_t never = 0, any = 0;
+#pragma unroll
+            for (int q = 0; q < kBcGroups; ++q) {
+                const uint32_t mask = q < 9 ? ((((gt.sel_a_bits >> q) & 1u) ? famA : famB) & Y[q])
+                                            : (famC & Y[q - 4]);
+                need[q] = ((gt.rng_bits >> q) & 1u) ? mask : 0u;
+                never |= ((gt.never_bits >> q) & 1u) ? mask : 0u;
+                any |= need[q];
+            }
+            const uint32_t always = ~(any | never);
+            const uint32_t F = metropolis_accept<kBcGroups>(need, thr, always, i, w, t, c, lat.key0, lat.key1);
+            const uint32_t zp = ~s.z | X;          // proposed s' != 0
+            const uint32_t sp = X & ~(s.z & s.s);  // proposed s' < 0
+            const uint32_t nz = (F & zp) | (~F & s.z);
+            const uint32_t ns = (F & sp) | (~F & s.s);
+            uint2 out;
+            out.x = nz;
+            out.y = ns;
+            reinterpret_cast<uint2 *>(own)[idx] = out;
+            if (MEASURE) {
+                e[0] += __popc(nz) + __popc(cur.z);
+                e[1] += __popc(ns) + __popc(cur.s);
+#pragma unroll
+                for (int n = 0; n < 4; ++n) {
+                    const uint32_t both = nz & nbr[n].z;
+                    e[2] += __popc(both);
+                    e[3] += __popc(both & (ns ^ nbr[n].s));
+                }
+            }
+            up = cur;
+            cur = dn;
+        }
+    }
+    if (MEASURE)
+        block_reduce_atomic<kEmCounters>(e, acc);
+}
+
+// ------------------------------------------ energy / magnetisation sums --
+
+template <int MODEL>
+__global__ __launch_bounds__(kBlock) void k_measure_em(Lattice lat, unsigned long long *acc)
+{
+    // Walks the colour-1 plane: every bond has exactly one colour-1 end, and
+    // word (i, w) of plane 0 is counted once as the same-row word.
+    const uint32_t L = lat.L, W = lat.W;
+    const uint32_t *p1 = lat.planes + lat.plane_u32;
+    const uint32_t *p0 = lat.planes;
+    const uint64_t nitems = (uint64_t)L * W;
+    unsigned long long e[kEmCounters] = {0, 0, 0, 0};
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nitems;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = (uint32_t)(g / W);
+        const uint32_t w = (uint32_t)(g - (uint64_t)i * W);
+        const uint32_t iu = i == 0 ? L - 1 : i - 1, id = i + 1 == L ? 0 : i + 1;
+        const uint32_t odd = (i + 1u) & 1u;
+        const uint32_t wn = odd ? (w + 1 == W ? 0 : w + 1) : (w == 0 ? W : w) - 1;
+        Pair s, up, dn, cur, nbw;
+        if (MODEL == kIsing) {
+            s = Pair{~0u, p1[g]};
+            up = Pair{~0u, p0[(size_t)iu * W + w]};
+            dn = Pair{~0u, p0[(size_t)id * W + w]};
+            cur = Pair{~0u, p0[g]};
+            nbw = Pair{~0u, p0[(size_t)i * W + wn]};
+        } else {
+            s = load_pair(p1, g);
+            up = load_pair(p0, (size_t)iu * W + w);
+            dn = load_pair(p0, (size_t)id * W + w);
+            cur = load_pair(p0, g);
+            nbw = load_pair(p0, (size_t)i * W + wn);
+        }
+        const Pair side{side_word(cur.z, nbw.z, odd), side_word(cur.s, nbw.s, odd)};
+        const Pair nbr[4] = {up, dn, cur, side};
+        e[0] += __popc(s.z) + __popc(cur.z);
+        e[1] += __popc(s.s) + __popc(cur.s);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const uint32_t both = s.z & nbr[n].z;
+            e[2] += __popc(both);
+            e[3] += __popc(both & (s.s ^ nbr[n].s));
+        }
+    }
+    block_reduce_atomic<kEmCounters>(e, acc);
+}
+
+// ------------------------------------------------------- correlations --
+
+struct RList {
+    uint32_t r[kCorrChunk];
+};
+
+template <int MODEL, bool VERTICAL>
+__global__ __launch_bounds__(kBlock) void k_corr(Lattice lat, RList rl, int n_r, unsigned long long *acc)
+{
+    const uint32_t L = lat.L, W = lat.W, half = L / 2;
+    const uint64_t per_plane = (uint64_t)L * W;
+    const uint64_t nitems = 2 * per_plane;
+    unsigned long long cnt[2 * kCorrChunk];
+#pragma unroll
+    for (int q = 0; q < 2 * kCorrChunk; ++q)
+        cnt[q] = 0;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nitems;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t c = g >= per_plane;
+        const uint64_t rem = g - (c ? per_plane : 0);
+        const uint32_t i = (uint32_t)(rem / W);
+        const uint32_t w = (uint32_t)(rem - (uint64_t)i * W);
+        const uint32_t *pc = lat.planes + (c ? lat.plane_u32 : 0);
+        Pair a;
+        if (MODEL == kIsing)
+            a = Pair{~0u, pc[rem]};
+        else
+            a = load_pair(pc, rem);
+#pragma unroll
+        for (int q = 0; q < kCorrChunk; ++q) {
+            if (q >= n_r)
+                break;
+            const uint32_t r = rl.r[q];
+            const uint32_t tc = c ^ (r & 1u);
+            const uint32_t *pt = lat.planes + (tc ? lat.plane_u32 : 0);
+            Pair b;
+            if (VERTICAL) {
+                // partner (i + r, j): same m in row i + r of plane c ^ (r & 1)
+                uint32_t ti = i + r;
+                if (ti >= L)
+                    ti -= L;
+                const size_t word = (size_t)ti * W + w;
+                b = MODEL == kIsing ? Pair{~0u, pt[word]} : load_pair(pt, word);
+            } else {
+                // partner (i, j + r): m + r/2 in the same plane for even r,
+                // m + (r - 1)/2 + ((i + c) & 1) in the other plane for odd r
+                uint32_t sh = (r >> 1) + ((r & 1u) & ((i + c) & 1u));
+                if (sh >= half)
+                    sh -= half;
+                uint32_t wa = w + (sh >> 5);
+                if (wa >= W)
+                    wa -= W;
+                const uint32_t wb = wa + 1 == W ? 0 : wa + 1;
+                const uint32_t rr = sh & 31u;
+                const size_t base = (size_t)i * W;
+                Pair x, y;
+                if (MODEL == kIsing) {
+                    x = Pair{~0u, pt[base + wa]};
+                    y = Pair{~0u, pt[base + wb]};
+                } else {
+                    x = load_pair(pt, base + wa);
+                    y = load_pair(pt, base + wb);
+                }
+                if (rr) {
+                    b.z = (x.z >> rr) | (y.z << (32u - rr));
+                    b.s = (x.s >> rr) | (y.s << (32u - rr));
+                } else {
+                    b = x;
+                }
+            }
+            const uint32_t both = a.z & b.z;
+            cnt[2 * q] += __popc(both);
+            cnt[2 * q + 1] += __popc(both & (a.s ^ b.s));
+        }
+    }
+    block_reduce_atomic<2 * kCorrChunk>(cnt, acc);
+}
+
+// ------------------------------------------------------------- helpers --
+
+__global__ void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v)
+{
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+         g += (uint64_t)gridDim.x * blockDim.x)
+        p[g] = v;
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(kBlock) void k_window(Lattice lat, uint32_t i0, uint32_t j0, uint32_t rows,
+                                                   uint32_t cols, int8_t *out)
+{
+    const uint32_t L = lat.L, W = lat.W;
+    const uint64_t n = (uint64_t)rows * cols;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t a = (uint32_t)(g / cols);
+        const uint32_t b = (uint32_t)(g - (uint64_t)a * cols);
+        uint32_t i = i0 + a, j = j0 + b;
+        if (i >= L)
+            i -= L;
+        if (j >= L)
+            j -= L;
+        const uint32_t c = (i + j) & 1u;
+        const uint32_t m = j >> 1;
+        const size_t word = (size_t)i * W + (m >> 5);
+        const uint32_t bit = m & 31u;
+        const uint32_t *pc = lat.planes + (c ? lat.plane_u32 : 0);
+        int8_t v;
+        if (MODEL == kIsing) {
+            v = ((pc[word] >> bit) & 1u) ? -1 : 1;
+        } else {
+            const Pair p = load_pair(pc, word);
+            v = ((p.z >> bit) & 1u) ? (((p.s >> bit) & 1u) ? -1 : 1) : 0;
+        }
+        out[g] = v;
+    }
+}
+
+} // namespace
+
+hipError_t launch_init(const Lattice &lat, hipStream_t st)
+{
+    if (lat.model == kIsing) {
+        hipLaunchKernelGGL(k_init_ising, dim3(grid_for(2 * lat.plane_u32)), dim3(kBlock), 0, st, lat.planes,
+                           lat.L, lat.W, lat.plane_u32, lat.key0, lat.key1);
+    } else {
+        hipLaunchKernelGGL(k_init_bc, dim3(grid_for(lat.plane_u32)), dim3(kBlock), 0, st, lat.planes, lat.L,
+                           lat.W, lat.plane_u32, lat.key0, lat.key1);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_half_sweep(const Lattice &lat, uint32_t colour, uint32_t t, const GroupTable &gt,
+                             unsigned long long *em_acc, hipStream_t st)
+{
+    const uint64_t items = (uint64_t)(lat.L / kRows) * lat.W;
+    const dim3 grid(grid_for(items)), block(kBlock);
+    if (lat.model == kIsing) {
+        if (em_acc)
+            hipLaunchKernelGGL(k_sweep_ising<true>, grid, block, 0, st, lat, colour, t, gt, em_acc);
+        else
+            hipLaunchKernelGGL(k_sweep_ising<false>, grid, block, 0, st, lat, colour, t, gt, em_acc);
+    } else {
+        if (em_acc)
+            hipLaunchKernelGGL(k_sweep_bc<true>, grid, block, 0, st, lat, colour, t, gt, em_acc);
+        else
+            hipLaunchKernelGGL(k_sweep_bc<false>, grid, block, 0, st, lat, colour, t, gt, em_acc);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_measure_em(const Lattice &lat, unsigned long long *em_acc, hipStream_t st)
+{
+    const dim3 grid(grid_for((uint64_t)lat.L * lat.W)), block(kBlock);
+    if (lat.model == kIsing)
+        hipLaunchKernelGGL(k_measure_em<kIsing>, grid, block, 0, st, lat, em_acc);
+    else
+        hipLaunchKernelGGL(k_measure_em<kBlumeCapel>, grid, block, 0, st, lat, em_acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_corr(const Lattice &lat, bool vertical, const uint32_t *r, int n_r,
+                       unsigned long long *acc, hipStream_t st)
+{
+    if (n_r <= 0 || n_r > kCorrChunk)
+        return hipErrorInvalidValue;
+    RList rl;
+    for (int q = 0; q < kCorrChunk; ++q)
+        rl.r[q] = q < n_r ? r[q] : 0u;
+    const dim3 grid(grid_for(2ull * lat.L * lat.W)), block(kBlock);
+    if (lat.model == kIsing) {
+        if (vertical)
+            hipLaunchKernelGGL((k_corr<kIsing, true>), grid, block, 0, st, lat, rl, n_r, acc);
+        else
+            hipLaunchKernelGGL((k_corr<kIsing, false>), grid, block, 0, st, lat, rl, n_r, acc);
+    } else {
+        if (vertical)
+            hipLaunchKernelGGL((k_corr<kBlumeCapel, true>), grid, block, 0, st, lat, rl, n_r, acc);
+        else
+            hipLaunchKernelGGL((k_corr<kBlumeCapel, false>), grid, block, 0, st, lat, rl, n_r, acc);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n)), dim3(kBlock), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_window(const Lattice &lat, uint32_t i0, uint32_t j0, uint32_t rows, uint32_t cols,
+                         int8_t *out, hipStream_t st)
+{
+    const dim3 grid(grid_for((uint64_t)rows * cols)), block(kBlock);
+    if (lat.model == kIsing)
+        hipLaunchKernelGGL(k_window<kIsing>, grid, block, 0, st, lat, i0, j0, rows, cols, out);
+    else
+        hipLaunchKernelGGL(k_window<kBlumeCapel>, grid, block, 0, st, lat, i0, j0, rows, cols, out);
+    return hipGetLastError();
+}
+
+} // namespace spin

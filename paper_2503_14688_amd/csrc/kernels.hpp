@@ -1,0 +1,55 @@
+// Internal launch interface between the C ABI (spin.hip) and the gfx950
+// kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spin {
+
+enum Model : int { kIsing = 0, kBlumeCapel = 1 };
+
+// Acceptance groups: Ising uses 2 (dE = 4J, 8J); Blume-Capel uses 13 --
+// nine for the pair {s -> 0, 0 -> s'} at y = -4..4 (exactly one of the two
+// families can have dE > 0 for a given y) and four for s -> -s at y = 1..4.
+constexpr int kIsingGroups = 2;
+constexpr int kBcGroups = 13;
+constexpr int kMaxGroups = 16;
+
+struct GroupTable {
+    uint32_t thr[kMaxGroups];   // integer threshold of the group
+    uint32_t rng_bits;          // bit g: group g needs a random number
+    uint32_t never_bits;        // bit g: group g is never accepted (T = 0)
+    uint32_t sel_a_bits;        // Blume-Capel: bit v (y = v - 4): the group's
+                                // positive family is s -> 0 (else 0 -> s')
+};
+
+struct Lattice {
+    uint32_t *planes;  // colour plane 0, then colour plane 1
+    uint32_t L;        // linear size
+    uint32_t W;        // 32-bit words per plane row (L / 64)
+    uint64_t plane_u32;// uint32 words per colour plane (L * W, doubled for BC)
+    int model;
+    uint32_t key0, key1;
+};
+
+// Counters of the energy/magnetisation reduction (both colours):
+//   acc[0] = #(s != 0)  acc[1] = #(s < 0)
+//   acc[2] = #bonds with both ends non-zero, acc[3] = #such bonds anti-aligned
+// so sum s = acc0 - 2 acc1, sum s^2 = acc0, bond sum = acc2 - 2 acc3.
+constexpr int kEmCounters = 4;
+
+hipError_t launch_init(const Lattice &lat, hipStream_t st);
+hipError_t launch_half_sweep(const Lattice &lat, uint32_t colour, uint32_t t, const GroupTable &gt,
+                             unsigned long long *em_acc, hipStream_t st);
+hipError_t launch_measure_em(const Lattice &lat, unsigned long long *em_acc, hipStream_t st);
+// Correlation counters for n_r (<= 8) separations: acc[2q] = #pairs with both
+// ends non-zero, acc[2q + 1] = #such pairs anti-aligned; S(r) = a - 2 b.
+constexpr int kCorrChunk = 8;
+hipError_t launch_corr(const Lattice &lat, bool vertical, const uint32_t *r, int n_r,
+                       unsigned long long *acc, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t st);
+hipError_t launch_window(const Lattice &lat, uint32_t i0, uint32_t j0, uint32_t rows, uint32_t cols,
+                         int8_t *out, hipStream_t st);
+
+} // namespace spin

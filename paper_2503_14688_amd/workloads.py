@@ -1,0 +1,93 @@
+"""Seeded synthetic inputs shared by the library's users, the tests and the
+benchmark: seeds, bath temperatures, separation sets and workload mixes.
+
+Holds none of the dynamics' arithmetic (no thresholds, no schedules, no
+observables); both the HIP path and the CPU oracle receive these inputs.
+The paper's workloads are synthetic by construction (disordered T = infinity
+starts, paper Thermal protocols), so nothing here stands in for a dataset.
+"""
+import math
+
+import numpy as np
+
+SEED_BASE = 2503146880
+
+# Ising T_c = 2 / ln(1 + sqrt 2) (paper, Models); Blume-Capel (Delta = 0)
+# T_c as simulated in Table I; the L = 2^18 Blume-Capel workload runs at
+# T = 1.6937 as specified for it.
+TC_ISING = 2.0 / math.log(1.0 + math.sqrt(2.0))
+TC_BC = 1.69355839821214427017
+T_BC_WORKLOAD = 1.6937
+
+
+def seed_for(k: int) -> int:
+    """Seed of replica or job k."""
+    return SEED_BASE + int(k)
+
+
+def r_sparse(L: int, r_max: int = 4096):
+    """Sparse separations: r = 1..16 and round(16 * 2^(k/4)), k = 1..32,
+    capped at min(r_max, L / 2) (the paper samples C(r) sparsely, App. C)."""
+    cap = min(r_max, L // 2)
+    rs = set(range(1, 17))
+    for k in range(1, 33):
+        rs.add(int(round(16.0 * 2.0 ** (k / 4.0))))
+    return np.array(sorted(r for r in rs if r <= cap), dtype=np.uint32)
+
+
+def r_dense(L: int):
+    """Every separation 1..L/2."""
+    return np.arange(1, L // 2 + 1, dtype=np.uint32)
+
+
+def measure_times(n_sweeps: int):
+    """Measurement points: after 0 sweeps and after 2^k sweeps."""
+    ts = [0]
+    k = 1
+    while k <= n_sweeps:
+        ts.append(k)
+        k *= 2
+    return ts
+
+
+# Workloads (the sizes and parameters of the benchmark configurations).
+ISING_SMALL = dict(name="ising_L64_tc", model=0, L=64, sweeps=1024, T=TC_ISING, seed=SEED_BASE)
+ISING_LARGE = dict(name="ising_L1048576_tc", model=0, L=1 << 20, sweeps=64, T=TC_ISING, seed=SEED_BASE)
+ISING_CHECK = dict(name="ising_L4096_tc", model=0, L=1 << 12, sweeps=64, T=TC_ISING, seed=SEED_BASE)
+BC_LARGE = dict(name="bc_L262144_t16937", model=1, L=1 << 18, sweeps=256, T=T_BC_WORKLOAD, seed=SEED_BASE,
+                J=1.0, Delta=0.0)
+BC_CHECK = dict(name="bc_L4096_t16937", model=1, L=1 << 12, sweeps=32, T=T_BC_WORKLOAD, seed=SEED_BASE,
+                J=1.0, Delta=0.0)
+
+
+def batched_replicas(n=512, sizes=(256, 512, 1024, 2048), taus=(64.0, 256.0, 1024.0)):
+    """Replica descriptors of the batched exponential-schedule workload:
+    uniform mix of sizes, half Ising and half Blume-Capel (Delta = 0), tau
+    round-robin, T0 = 2 T_c and T_f = 1.02 T_c with each model's own T_c."""
+    reps = []
+    for k in range(n):
+        model = k % 2
+        L = sizes[(k // 2) % len(sizes)]
+        tau = taus[k % len(taus)]
+        tc = TC_ISING if model == 0 else TC_BC
+        reps.append(dict(id=k, model=model, L=L, seed=seed_for(k), J=1.0, Delta=0.0,
+                         T0=2.0 * tc, Tf=1.02 * tc, tau=tau))
+    return reps
+
+
+def serving_jobs(n, rate_per_s, seed=SEED_BASE, log2_L=(8, 14), log2_sweeps=(10, 14)):
+    """Poisson stream of quench jobs: arrival times (s), L = 2^U with U uniform
+    in log2_L, model Bernoulli(1/2), sweeps 2^V with V uniform in
+    log2_sweeps, each at its model's T_c."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate_per_s, size=n)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    jobs = []
+    for k in range(n):
+        model = int(rng.integers(0, 2))
+        L = 1 << int(rng.integers(log2_L[0], log2_L[1] + 1))
+        sweeps = 1 << int(rng.integers(log2_sweeps[0], log2_sweeps[1] + 1))
+        jobs.append(dict(id=k, arrival=float(arrivals[k]), model=model, L=L, sweeps=sweeps,
+                         seed=seed_for(10_000_000 + k), J=1.0, Delta=0.0,
+                         T=TC_ISING if model == 0 else TC_BC))
+    return jobs
