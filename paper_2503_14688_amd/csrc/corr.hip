@@ -1,0 +1,352 @@
+// Correlation sums S_x(r), S_y(r) (paper Eq. 2, App. C) for the sparse
+// separation set r in {1..16} u {round(16 * 2^(k/4)), k = 1..32}, i.e. up to
+// r = 4096, on gfx950.
+//
+// Horizontal (k_corr_x_sparse): a block stages one row segment of both
+// colour planes in LDS with a 66-word halo; every separation is a fixed bit
+// shift of the partner plane (r even: same colour, m + r/2; r odd: other
+// colour, m + (r-1)/2 + ((i + c) & 1)), so with the set known at compile time
+// each pair costs one funnel shift, one XOR and one accumulating popcount.
+//
+// Vertical (k_corr_y_ring): a block owns a 4-word (Ising) or 2-word
+// (Blume-Capel) column strip of both planes and walks down the lattice once,
+// keeping the last r_max + chunk rows in an LDS ring; each new row meets its
+// 48 partners above it in the ring, so the lattice is read from HBM about
+// once for all separations.
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace spin {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kSparseN = 48;
+
+__host__ __device__ constexpr uint32_t sparse_r(int q)
+{
+    if (q < 16)
+        return (uint32_t)q + 1u;
+    switch (q) {
+    case 16: return 19;   case 17: return 23;   case 18: return 27;   case 19: return 32;
+    case 20: return 38;   case 21: return 45;   case 22: return 54;   case 23: return 64;
+    case 24: return 76;   case 25: return 91;   case 26: return 108;  case 27: return 128;
+    case 28: return 152;  case 29: return 181;  case 30: return 215;  case 31: return 256;
+    case 32: return 304;  case 33: return 362;  case 34: return 431;  case 35: return 512;
+    case 36: return 609;  case 37: return 724;  case 38: return 861;  case 39: return 1024;
+    case 40: return 1218; case 41: return 1448; case 42: return 1722; case 43: return 2048;
+    case 44: return 2435; case 45: return 2896; case 46: return 3444; default: return 4096;
+    }
+}
+
+// ------------------------------------------------------------ horizontal --
+
+constexpr int kTileW = 1024;  // words of a row segment per block iteration
+constexpr int kHalo = 66;     // (4096 / 2 + 1) / 32 + 2 words of shifted partners
+
+template <int MODEL>
+struct XTile {
+    static constexpr int E = MODEL == kIsing ? 1 : 2;  // uint32 per word (S) or (Z, S)
+    uint32_t w[2][(kTileW + kHalo) * E];
+};
+
+// Pairs of one own word (plane C, row parity P) with all requested r.
+template <int MODEL, int C, int P, int Q>
+__device__ __forceinline__ void x_pairs(const XTile<MODEL> &t, int k, uint32_t oz, uint32_t os, int n_r,
+                                        uint32_t (&ca)[kSparseN], uint32_t (&cb)[kSparseN])
+{
+    if constexpr (Q < kSparseN) {
+        if (Q < n_r) {
+            constexpr uint32_t r = sparse_r(Q);
+            constexpr int tc = C ^ (int)(r & 1u);
+            constexpr uint32_t s = (r >> 1) + ((r & 1u) & (uint32_t)P);
+            constexpr int qw = (int)(s >> 5);
+            constexpr uint32_t rr = s & 31u;
+            constexpr int E = XTile<MODEL>::E;
+            if constexpr (MODEL == kIsing) {
+                const uint32_t x = t.w[tc][k + qw], y = t.w[tc][k + qw + 1];
+                const uint32_t b = rr ? __builtin_amdgcn_alignbit(y, x, rr) : x;
+                cb[Q] += __popc(os ^ b);
+            } else {
+                const uint32_t xz = t.w[tc][(k + qw) * E], yz = t.w[tc][(k + qw + 1) * E];
+                const uint32_t xs = t.w[tc][(k + qw) * E + 1], ys = t.w[tc][(k + qw + 1) * E + 1];
+                const uint32_t bz = rr ? __builtin_amdgcn_alignbit(yz, xz, rr) : xz;
+                const uint32_t bs = rr ? __builtin_amdgcn_alignbit(ys, xs, rr) : xs;
+                const uint32_t both = oz & bz;
+                ca[Q] += __popc(both);
+                cb[Q] += __popc(both & (os ^ bs));
+            }
+        }
+        x_pairs<MODEL, C, P, Q + 1>(t, k, oz, os, n_r, ca, cb);
+    }
+}
+
+template <int MODEL, int C>
+__device__ __forceinline__ void x_word(const XTile<MODEL> &t, int k, uint32_t parity, int n_r,
+                                       uint32_t (&ca)[kSparseN], uint32_t (&cb)[kSparseN])
+{
+    constexpr int E = XTile<MODEL>::E;
+    const uint32_t oz = MODEL == kIsing ? ~0u : t.w[C][k * E];
+    const uint32_t os = t.w[C][k * E + (E - 1)];
+    if (parity)
+        x_pairs<MODEL, C, 1, 0>(t, k, oz, os, n_r, ca, cb);
+    else
+        x_pairs<MODEL, C, 0, 0>(t, k, oz, os, n_r, ca, cb);
+}
+
+template <int N>
+__device__ __forceinline__ void flush_counts(const uint32_t (&cnt)[N], int n_r, unsigned long long *dst,
+                                             int stride)
+{
+    // block sum of each counter, one atomic per counter and block
+    __shared__ unsigned long long part[N];
+    for (int q = threadIdx.x; q < N; q += blockDim.x)
+        part[q] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        unsigned long long x = cnt[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            x += __shfl_xor(x, off, 64);
+        if ((threadIdx.x & 63) == 0 && q < n_r)
+            atomicAdd(&part[q], x);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < n_r && q < N; q += blockDim.x)
+        if (part[q])
+            atomicAdd(dst + (size_t)q * stride, part[q]);
+    __syncthreads();
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(kBlock) void k_corr_x_sparse(Lattice lat, int n_r, unsigned long long *acc)
+{
+    __shared__ XTile<MODEL> t;
+    constexpr int E = XTile<MODEL>::E;
+    const uint32_t L = lat.L, W = lat.W;
+    const uint32_t tiles_per_row = (W + kTileW - 1) / kTileW;
+    const uint64_t ntiles = (uint64_t)L * tiles_per_row;
+    uint32_t ca[kSparseN], cb[kSparseN];
+#pragma unroll
+    for (int q = 0; q < kSparseN; ++q) {
+        ca[q] = 0;
+        cb[q] = 0;
+    }
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t i = (uint32_t)(tile / tiles_per_row);
+        const uint32_t w0 = (uint32_t)(tile - (uint64_t)i * tiles_per_row) * kTileW;
+        const int tw = (int)(W - w0 < (uint32_t)kTileW ? W - w0 : (uint32_t)kTileW);
+        __syncthreads();
+        for (int k = threadIdx.x; k < (tw + kHalo) * E; k += kBlock) {
+            const int e = k / E, part = k - e * E;
+            const uint32_t wk = (w0 + (uint32_t)e) % W;
+            const size_t off = ((size_t)i * W + wk) * E + part;
+            t.w[0][k] = lat.planes[off];
+            t.w[1][k] = lat.planes[lat.plane_u32 + off];
+        }
+        __syncthreads();
+        const uint32_t p0 = i & 1u;  // row parity of colour 0; colour 1 has the other
+        for (int k = threadIdx.x; k < tw; k += kBlock) {
+            x_word<MODEL, 0>(t, k, p0, n_r, ca, cb);
+            x_word<MODEL, 1>(t, k, p0 ^ 1u, n_r, ca, cb);
+        }
+    }
+    if (MODEL != kIsing)
+        flush_counts<kSparseN>(ca, n_r, acc, 2);
+    flush_counts<kSparseN>(cb, n_r, acc + 1, 2);
+}
+
+// -------------------------------------------------------------- vertical --
+
+// A ring row is 8 uint32: Ising words [w0, w0 + 4) of plane 0 then plane 1;
+// Blume-Capel (Z, S) of words [w0, w0 + 2) of plane 0 then plane 1.
+constexpr int kRingCols = 8;
+
+template <int MODEL>
+struct YShape {
+    static constexpr int CH = MODEL == kIsing ? 32 : 64;          // rows per chunk
+    static constexpr int SW = MODEL == kIsing ? 4 : 2;            // words per plane in the strip
+    static constexpr int TPR = kBlock / CH;                        // threads per chunk row
+};
+
+template <int MODEL, int Q>
+__device__ __forceinline__ void y_pairs(const uint32_t *ring, uint32_t ring_base, int jr, int col, uint32_t xe,
+                                        uint32_t xo, uint32_t xse, uint32_t xso, int64_t j, uint32_t L,
+                                        bool all_valid, int n_r, uint32_t (&ca)[kSparseN],
+                                        uint32_t (&cb)[kSparseN], uint32_t RING)
+{
+    if constexpr (Q < kSparseN) {
+        if (Q < n_r) {
+            constexpr uint32_t r = sparse_r(Q);
+            // slot of base row j - r: (slot(j0) - r) mod RING + jr, mirrored past RING
+            uint32_t base = ring_base + RING - (r % RING);
+            if (base >= RING)
+                base -= RING;
+            const int64_t i = j - (int64_t)r;
+            const bool ok = all_valid || (i >= 0 && i < (int64_t)L);
+            const uint32_t *row = ring + (size_t)(base + (uint32_t)jr) * kRingCols;
+            if (MODEL == kIsing) {
+                const uint32_t b = row[col];
+                const uint32_t x = (r & 1u) ? xo : xe;
+                if (ok)
+                    cb[Q] += __popc(b ^ x);
+            } else {
+                const uint32_t bz = row[col], bs = row[col + 1];
+                const uint32_t xz = (r & 1u) ? xo : xe, xs = (r & 1u) ? xso : xse;
+                const uint32_t both = bz & xz;
+                if (ok) {
+                    ca[Q] += __popc(both);
+                    cb[Q] += __popc(both & (bs ^ xs));
+                }
+            }
+        }
+        y_pairs<MODEL, Q + 1>(ring, ring_base, jr, col, xe, xo, xse, xso, j, L, all_valid, n_r, ca, cb, RING);
+    }
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(kBlock) void k_corr_y_ring(Lattice lat, int n_r, uint32_t RING,
+                                                        unsigned long long *acc)
+{
+    extern __shared__ uint32_t ring[];  // (RING + CH) rows of kRingCols words
+    using S = YShape<MODEL>;
+    constexpr int CH = S::CH, SW = S::SW;
+    constexpr int E = MODEL == kIsing ? 1 : 2;
+    const uint32_t L = lat.L, W = lat.W;
+    const uint32_t strips = W / SW;
+    const uint32_t r_max = sparse_r(n_r - 1);
+    const int64_t rows_total = (int64_t)L + r_max;  // partner rows j = 0 .. L + r_max - 1
+    const int64_t nchunks = (rows_total + CH - 1) / CH;
+    // loading: CH rows x 8 words, LPT words per thread
+    constexpr int LPT = CH * kRingCols / kBlock;
+    // compute: thread -> (chunk row jr, column); Ising one word column, BC one (Z,S) column
+    const int jr = threadIdx.x / S::TPR;
+    const int lane_col = threadIdx.x % S::TPR;           // Ising 0..7, BC 0..3
+    const int col = MODEL == kIsing ? lane_col : 2 * lane_col;  // ring column of the base word
+    // partner column in the other plane: columns 0..3 are plane 0, 4..7 plane 1
+    const int col_other = col ^ 4;
+    uint32_t ca[kSparseN], cb[kSparseN];
+#pragma unroll
+    for (int q = 0; q < kSparseN; ++q) {
+        ca[q] = 0;
+        cb[q] = 0;
+    }
+    for (uint32_t strip = blockIdx.x; strip < strips; strip += gridDim.x) {
+        const uint32_t w0 = strip * SW;
+        uint32_t pre[LPT];
+        auto load_chunk = [&](int64_t j0) {
+#pragma unroll
+            for (int q = 0; q < LPT; ++q) {
+                const int idx = threadIdx.x + q * kBlock;  // 0 .. CH * 8 - 1
+                const int row = idx / kRingCols, c8 = idx % kRingCols;
+                const int64_t j = j0 + row;
+                const uint32_t jg = (uint32_t)(j % (int64_t)L);
+                const int plane = c8 >> 2, within = c8 & 3;  // within: word (Ising) or word*2+part (BC)
+                const size_t off = ((size_t)jg * W + w0) * E + (size_t)within;
+                pre[q] = lat.planes[(plane ? lat.plane_u32 : 0) + off];
+            }
+        };
+        __syncthreads();
+        load_chunk(0);
+        for (int64_t ch = 0; ch < nchunks; ++ch) {
+            const int64_t j0 = ch * CH;
+            const uint32_t slot0 = (uint32_t)(j0 % (int64_t)RING);  // multiple of CH
+#pragma unroll
+            for (int q = 0; q < LPT; ++q) {
+                const int idx = threadIdx.x + q * kBlock;
+                const int row = idx / kRingCols, c8 = idx % kRingCols;
+                ring[(size_t)(slot0 + row) * kRingCols + c8] = pre[q];
+                if (slot0 == 0)
+                    ring[(size_t)(RING + row) * kRingCols + c8] = pre[q];
+            }
+            __syncthreads();
+            if (ch + 1 < nchunks)
+                load_chunk(j0 + CH);
+            const int64_t j = j0 + jr;
+            const uint32_t *me = ring + (size_t)(slot0 + jr) * kRingCols;
+            const uint32_t xe = me[col], xo = me[col_other];
+            const uint32_t xse = MODEL == kIsing ? 0u : me[col + 1];
+            const uint32_t xso = MODEL == kIsing ? 0u : me[col_other + 1];
+            // every pair of the chunk is valid when j0 - r >= 0 and j0 + CH - 1 - r < L for all r
+            const bool all_valid = j0 >= (int64_t)r_max && j0 + CH - 1 < (int64_t)L + 1;
+            y_pairs<MODEL, 0>(ring, slot0, jr, col, xe, xo, xse, xso, j, L, all_valid, n_r, ca, cb, RING);
+            __syncthreads();
+        }
+    }
+    if (MODEL != kIsing)
+        flush_counts<kSparseN>(ca, n_r, acc, 2);
+    flush_counts<kSparseN>(cb, n_r, acc + 1, 2);
+}
+
+} // namespace
+
+bool sparse_prefix(const uint32_t *r, int n_r)
+{
+    if (n_r <= 0 || n_r > kSparseN)
+        return false;
+    for (int q = 0; q < n_r; ++q)
+        if (r[q] != sparse_r(q))
+            return false;
+    return true;
+}
+
+bool corr_sparse_x_ok(const Lattice &lat, const uint32_t *r, int n_r)
+{
+    (void)lat;
+    return sparse_prefix(r, n_r);
+}
+
+bool corr_sparse_y_ok(const Lattice &lat, const uint32_t *r, int n_r)
+{
+    const uint32_t sw = lat.model == kIsing ? YShape<kIsing>::SW : YShape<kBlumeCapel>::SW;
+    return sparse_prefix(r, n_r) && lat.W % sw == 0;
+}
+
+static unsigned corr_grid(uint64_t items, unsigned cap)
+{
+    uint64_t g = items < cap ? items : cap;
+    return (unsigned)(g ? g : 1);
+}
+
+hipError_t launch_corr_sparse(const Lattice &lat, bool vertical, int n_r, unsigned long long *acc, hipStream_t st)
+{
+    if (!vertical) {
+        const uint64_t tiles = (uint64_t)lat.L * ((lat.W + kTileW - 1) / kTileW);
+        const dim3 grid(corr_grid(tiles, 2048)), block(kBlock);
+        if (lat.model == kIsing)
+            hipLaunchKernelGGL(k_corr_x_sparse<kIsing>, grid, block, 0, st, lat, n_r, acc);
+        else
+            hipLaunchKernelGGL(k_corr_x_sparse<kBlumeCapel>, grid, block, 0, st, lat, n_r, acc);
+        return hipGetLastError();
+    }
+    const uint32_t r_max = sparse_r(n_r - 1);
+    if (lat.model == kIsing) {
+        constexpr int CH = YShape<kIsing>::CH;
+        const uint32_t RING = (r_max + CH + CH - 1) / CH * CH;
+        const size_t lds = (size_t)(RING + CH) * kRingCols * sizeof(uint32_t);
+        const dim3 grid(corr_grid(lat.W / YShape<kIsing>::SW, 256)), block(kBlock);
+        (void)hipFuncSetAttribute((const void *)k_corr_y_ring<kIsing>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_corr_y_ring<kIsing>, grid, block, lds, st, lat, n_r, RING, acc);
+    } else {
+        constexpr int CH = YShape<kBlumeCapel>::CH;
+        const uint32_t RING = (r_max + CH + CH - 1) / CH * CH;
+        const size_t lds = (size_t)(RING + CH) * kRingCols * sizeof(uint32_t);
+        const dim3 grid(corr_grid(lat.W / YShape<kBlumeCapel>::SW, 256)), block(kBlock);
+        (void)hipFuncSetAttribute((const void *)k_corr_y_ring<kBlumeCapel>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_corr_y_ring<kBlumeCapel>, grid, block, lds, st, lat, n_r, RING, acc);
+    }
+    return hipGetLastError();
+}
+
+size_t corr_sparse_y_lds(const Lattice &lat, int n_r)
+{
+    const int CH = lat.model == kIsing ? YShape<kIsing>::CH : YShape<kBlumeCapel>::CH;
+    const uint32_t r_max = sparse_r(n_r - 1);
+    const uint32_t RING = (r_max + CH + CH - 1) / CH * CH;
+    return (size_t)(RING + CH) * kRingCols * sizeof(uint32_t);
+}
+
+} // namespace spin

@@ -48,6 +48,14 @@ hipError_t launch_measure_em(const Lattice &lat, unsigned long long *em_acc, hip
 constexpr int kCorrChunk = 8;
 hipError_t launch_corr(const Lattice &lat, bool vertical, const uint32_t *r, int n_r,
                        unsigned long long *acc, hipStream_t st);
+// Sparse separation set r in {1..16} u {round(16 * 2^(k/4)), k = 1..32}: the
+// fast kernels take any prefix of it (counters laid out as launch_corr's).
+bool sparse_prefix(const uint32_t *r, int n_r);
+bool corr_sparse_x_ok(const Lattice &lat, const uint32_t *r, int n_r);
+bool corr_sparse_y_ok(const Lattice &lat, const uint32_t *r, int n_r);
+size_t corr_sparse_y_lds(const Lattice &lat, int n_r);
+hipError_t launch_corr_sparse(const Lattice &lat, bool vertical, int n_r, unsigned long long *acc,
+                              hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t st);
 hipError_t launch_window(const Lattice &lat, uint32_t i0, uint32_t j0, uint32_t rows, uint32_t cols,
                          int8_t *out, hipStream_t st);

@@ -330,12 +330,21 @@ int spin_measure(spin_handle *h, const uint32_t *r, uint32_t n_r, spin_meas *out
     }
     if (n_r > 0) {
         HIP_TRY(spin::launch_fill_u64(h->d_acc + base_x, 4 * (uint64_t)n_r, 0ull, h->stream), "fill kernel launch");
-        for (uint32_t q0 = 0; q0 < n_r; q0 += spin::kCorrChunk) {
-            const int cnt = (int)((n_r - q0) < (uint32_t)spin::kCorrChunk ? (n_r - q0) : spin::kCorrChunk);
-            HIP_TRY(spin::launch_corr(h->lat, false, r + q0, cnt, h->d_acc + base_x + 2 * q0, h->stream),
-                    "correlation kernel launch");
-            HIP_TRY(spin::launch_corr(h->lat, true, r + q0, cnt, h->d_acc + base_y + 2 * q0, h->stream),
-                    "correlation kernel launch");
+        for (int axis = 0; axis < 2; ++axis) {
+            const bool vertical = axis == 1;
+            unsigned long long *dst = h->d_acc + (vertical ? base_y : base_x);
+            const bool fast = vertical ? spin::corr_sparse_y_ok(h->lat, r, (int)n_r)
+                                       : spin::corr_sparse_x_ok(h->lat, r, (int)n_r);
+            if (fast) {
+                HIP_TRY(spin::launch_corr_sparse(h->lat, vertical, (int)n_r, dst, h->stream),
+                        "correlation kernel launch");
+                continue;
+            }
+            for (uint32_t q0 = 0; q0 < n_r; q0 += spin::kCorrChunk) {
+                const int cnt = (int)((n_r - q0) < (uint32_t)spin::kCorrChunk ? (n_r - q0) : spin::kCorrChunk);
+                HIP_TRY(spin::launch_corr(h->lat, vertical, r + q0, cnt, dst + 2 * q0, h->stream),
+                        "correlation kernel launch");
+            }
         }
     }
     std::vector<unsigned long long> acc(base_y + 2 * (size_t)n_r);
@@ -351,9 +360,13 @@ int spin_measure(spin_handle *h, const uint32_t *r, uint32_t n_r, spin_meas *out
     out->e = (-h->J * (double)out->bond + h->Delta * (double)out->sum_s2) / N;
     out->m = (double)out->sum_s / N;
     std::vector<double> rr(n_r), ch(n_r);
+    // pairs with both ends non-zero: every pair for Ising (L^2 per axis and r)
+    const int64_t all_pairs = (int64_t)h->L * (int64_t)h->L;
     for (uint32_t q = 0; q < n_r; ++q) {
-        Sx[q] = (int64_t)acc[base_x + 2 * q] - 2 * (int64_t)acc[base_x + 2 * q + 1];
-        Sy[q] = (int64_t)acc[base_y + 2 * q] - 2 * (int64_t)acc[base_y + 2 * q + 1];
+        const int64_t ax = h->model == SPIN_ISING ? all_pairs : (int64_t)acc[base_x + 2 * q];
+        const int64_t ay = h->model == SPIN_ISING ? all_pairs : (int64_t)acc[base_y + 2 * q];
+        Sx[q] = ax - 2 * (int64_t)acc[base_x + 2 * q + 1];
+        Sy[q] = ay - 2 * (int64_t)acc[base_y + 2 * q + 1];
         rr[q] = (double)r[q];
         ch[q] = (double)(Sx[q] + Sy[q]) / (2.0 * N);
         if (C_hat)

@@ -190,6 +190,21 @@ def test_invalid_arguments(gpu):
     lat.close()
 
 
+@pytest.mark.parametrize("model,L", [(0, 512), (1, 512), (0, 192), (1, 320)])
+def test_sparse_and_generic_correlation_kernels_agree(gpu, model, L):
+    """The sparse-set kernels (LDS tiles / LDS ring) against the generic ones
+    (a list that is not a prefix of the sparse set) and the oracle."""
+    lat = make(gpu, model, L, 13)
+    lat.sweep(np.full(4, 2.2 if model == 0 else 1.6))
+    r_fast = workloads.r_sparse(L)
+    r_slow = np.append(r_fast, np.uint32(r_fast[-1] + 1))
+    a, b = lat.measure(r_fast), lat.measure(r_slow)
+    n = len(r_fast)
+    assert np.array_equal(a["Sx"], b["Sx"][:n]) and np.array_equal(a["Sy"], b["Sy"][:n])
+    compare_measure(a, L, 1.0, 0.0, lat.spins(), r_fast)
+    lat.close()
+
+
 def test_ising_L4096_check_run(gpu):
     """The bit-exact check lattice of the large Ising workload: 2^12 x 2^12, 64 sweeps."""
     w = workloads.ISING_CHECK
