@@ -168,6 +168,65 @@ int spin_destroy(spin_handle *h);
 /* Thread-local description of the last failure on this thread. */
 const char *spin_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Batched replicas: many independent lattices (any mix of model and L), each
+ * with its own seed and bath-temperature schedule (paper, Thermal protocols:
+ * the quench of protocol 1 and the time-dependent bath of protocol 2),
+ * advanced together.  Every replica evolves exactly as it would alone
+ * through spin_sweep with the same T array.  One launch per half-sweep
+ * covers all replicas; a run of n sweeps is captured as one HIP graph.
+ * ------------------------------------------------------------------------ */
+
+typedef struct spin_batch spin_batch;
+
+typedef struct spin_replica_desc {
+    int model;          /* SPIN_ISING or SPIN_BLUME_CAPEL                      */
+    uint32_t L;         /* as for spin_create                                  */
+    uint64_t seed;
+    double J, Delta;
+    void *dev_buf;      /* caller-owned, spin_lattice_bytes(model, L) bytes    */
+    size_t buf_bytes;
+    uint32_t schedule;  /* row of the schedule table this replica follows      */
+} spin_replica_desc;
+
+/* spin_batch_run flags */
+#define SPIN_BATCH_DIRECT 1u  /* launch directly instead of capturing a graph */
+#define SPIN_BATCH_ROWS4 2u   /* force 4 rows per thread                      */
+#define SPIN_BATCH_ROWS8 4u   /* force 8 rows per thread                      */
+
+/* Create a batch of n replicas (all at t = 0).  T holds n_sched schedules of
+ * n_steps temperatures each: T[s * n_steps + k] is the bath temperature of
+ * sweep k for schedule s (host array, copied into threshold tables).  The
+ * batch owns one handle per replica (spin_batch_replica) and works on
+ * hip_stream, or on a stream of its own when hip_stream is NULL (a graph
+ * cannot be captured on the legacy default stream).  -EINVAL as for
+ * spin_create (message names the replica), or a schedule index out of range,
+ * or a negative / NaN temperature. */
+int spin_batch_create(uint32_t n, const spin_replica_desc *reps, uint32_t n_sched, uint32_t n_steps,
+                      const double *T, void *hip_stream, spin_batch **out);
+
+/* T = infinity start of every replica.  Asynchronous. */
+int spin_batch_init_random(spin_batch *b);
+
+/* Advance every replica by n sweeps (schedule steps t .. t + n - 1).  The
+ * first run chooses the tile shape (4 or 8 rows per thread) by timing both
+ * on scratch copies of the lattices, unless a ROWS flag forces one.
+ * Asynchronous; -EINVAL past the end of the schedule. */
+int spin_batch_run(spin_batch *b, uint32_t n, uint32_t flags);
+
+/* Wait for the batch's queued work. */
+int spin_batch_sync(spin_batch *b);
+
+/* Borrow replica k's handle (measure, get/set spins); owned by the batch. */
+int spin_batch_replica(spin_batch *b, uint32_t k, spin_handle **out);
+
+/* Replica count, sweeps done, tile shape in use (0 before the first run) and
+ * tiles per half-sweep; any output may be NULL. */
+int spin_batch_info(const spin_batch *b, uint32_t *n_replicas, uint64_t *t, int *rows, uint64_t *tiles);
+
+/* Release the batch, its handles and device tables (never the lattices). */
+int spin_batch_destroy(spin_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,10 +36,22 @@ class spin_meas(ctypes.Structure):
                 ("xi", ctypes.c_double)]
 
 
+BATCH_DIRECT = 1
+BATCH_ROWS4 = 2
+BATCH_ROWS8 = 4
+
+
+class spin_replica_desc(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int), ("L", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+                ("J", ctypes.c_double), ("Delta", ctypes.c_double), ("dev_buf", ctypes.c_void_p),
+                ("buf_bytes", ctypes.c_size_t), ("schedule", ctypes.c_uint32)]
+
+
 EXPORTS = ["spin_lattice_bytes", "spin_create", "spin_init_random", "spin_sweep", "spin_sweep_ex",
            "spin_measure", "spin_get_spins", "spin_get_window", "spin_set_spins", "spin_set_t",
            "spin_get_t", "spin_threshold_table", "spin_schedule_fill", "spin_destroy",
-           "spin_last_error"]
+           "spin_last_error", "spin_batch_create", "spin_batch_init_random", "spin_batch_run",
+           "spin_batch_sync", "spin_batch_replica", "spin_batch_info", "spin_batch_destroy"]
 
 
 def load_library():
@@ -78,6 +90,15 @@ def load_library():
                                               f64p]),
         "spin_destroy": (ctypes.c_int, [vp]),
         "spin_last_error": (ctypes.c_char_p, []),
+        "spin_batch_create": (ctypes.c_int, [ctypes.c_uint32, ctypes.POINTER(spin_replica_desc), ctypes.c_uint32,
+                                             ctypes.c_uint32, f64p, vp, ctypes.POINTER(vp)]),
+        "spin_batch_init_random": (ctypes.c_int, [vp]),
+        "spin_batch_run": (ctypes.c_int, [vp, ctypes.c_uint32, ctypes.c_uint32]),
+        "spin_batch_sync": (ctypes.c_int, [vp]),
+        "spin_batch_replica": (ctypes.c_int, [vp, ctypes.c_uint32, ctypes.POINTER(vp)]),
+        "spin_batch_info": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64),
+                                           ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_uint64)]),
+        "spin_batch_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -191,6 +212,48 @@ def spin_last_error():
     return load_library().spin_last_error().decode()
 
 
+def spin_batch_create(descs, T, hip_stream=0):
+    """descs: list of spin_replica_desc; T: (n_sched, n_steps) float64."""
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    arr = (spin_replica_desc * len(descs))(*descs)
+    b = ctypes.c_void_p()
+    _check(load_library().spin_batch_create(len(descs), arr, T.shape[0], T.shape[1], _ptr(T, ctypes.c_double),
+                                            ctypes.c_void_p(hip_stream), ctypes.byref(b)))
+    return b
+
+
+def spin_batch_init_random(b):
+    _check(load_library().spin_batch_init_random(b))
+
+
+def spin_batch_run(b, n, flags=0):
+    _check(load_library().spin_batch_run(b, n, flags))
+
+
+def spin_batch_sync(b):
+    _check(load_library().spin_batch_sync(b))
+
+
+def spin_batch_replica(b, k):
+    h = ctypes.c_void_p()
+    _check(load_library().spin_batch_replica(b, k, ctypes.byref(h)))
+    return h
+
+
+def spin_batch_info(b):
+    n = ctypes.c_uint32()
+    t = ctypes.c_uint64()
+    rows = ctypes.c_int()
+    tiles = ctypes.c_uint64()
+    _check(load_library().spin_batch_info(b, ctypes.byref(n), ctypes.byref(t), ctypes.byref(rows),
+                                          ctypes.byref(tiles)))
+    return {"replicas": n.value, "t": t.value, "rows": rows.value, "tiles": tiles.value}
+
+
+def spin_batch_destroy(b):
+    _check(load_library().spin_batch_destroy(b))
+
+
 # ------------------------------------------------- device-buffer holder --
 
 class Lattice:
@@ -240,6 +303,59 @@ class Lattice:
         if self.h is not None:
             spin_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Replicas in torch uint8 device buffers, advanced together by the C ABI.
+
+    reps: dicts with model, L, seed, J, Delta and schedule (row index of T).
+    """
+
+    def __init__(self, reps, T, device="cuda"):
+        import torch
+        self.reps = reps
+        self.bufs = []
+        descs = []
+        for r in reps:
+            nbytes = spin_lattice_bytes(r["model"], r["L"])
+            buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+            self.bufs.append(buf)
+            descs.append(spin_replica_desc(r["model"], r["L"], r["seed"], r.get("J", 1.0), r.get("Delta", 0.0),
+                                           buf.data_ptr(), nbytes, r["schedule"]))
+        self.b = spin_batch_create(descs, T)
+
+    def init_random(self):
+        spin_batch_init_random(self.b)
+        return self
+
+    def run(self, n, flags=0):
+        spin_batch_run(self.b, n, flags)
+
+    def sync(self):
+        spin_batch_sync(self.b)
+
+    def replica(self, k):
+        return spin_batch_replica(self.b, k)
+
+    def spins(self, k):
+        return spin_get_spins(self.replica(k), self.reps[k]["L"])
+
+    def measure(self, k, r=()):
+        return spin_measure(self.replica(k), r)
+
+    def info(self):
+        return spin_batch_info(self.b)
+
+    def close(self):
+        if self.b is not None:
+            spin_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

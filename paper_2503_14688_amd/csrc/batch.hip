@@ -1,0 +1,370 @@
+// Batched replicas (C ABI spin_batch_*): many independent lattices of mixed
+// size and model, each following its own bath-temperature schedule (paper,
+// Thermal protocols), advanced together by one launch per half-sweep over a
+// flat list of all replicas' tiles.  A run of n sweeps is captured once as a
+// HIP graph of 2n launches and replayed; the rows-per-thread tile shape is
+// chosen by timing both shapes on scratch copies of the lattices.
+#include "host.hpp"
+
+#include <algorithm>
+#include <cerrno>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+using namespace spin_host;
+
+struct spin_batch {
+    std::vector<spin_handle *> reps;
+    std::vector<uint32_t> table_of;     // replica -> threshold table id
+    uint32_t n_tables = 0, n_steps = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint64_t t = 0;                      // sweeps done (schedule step)
+    int rows = 0;                        // tile shape in use (4 or 8; 0 = tune at first run)
+    spin::BatchReplica *d_reps[2] = {nullptr, nullptr};  // per tile shape
+    uint32_t *d_tile_rep[2] = {nullptr, nullptr};
+    uint64_t ntiles[2] = {0, 0};
+    GroupTable *d_tables = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int shape_index(int rows) { return rows == 4 ? 0 : 1; }
+
+void release(spin_batch *b)
+{
+    if (!b)
+        return;
+    if (b->stream)
+        (void)hipStreamSynchronize(b->stream);
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    for (int k = 0; k < 2; ++k) {
+        if (b->d_reps[k])
+            (void)hipFree(b->d_reps[k]);
+        if (b->d_tile_rep[k])
+            (void)hipFree(b->d_tile_rep[k]);
+    }
+    if (b->d_tables)
+        (void)hipFree(b->d_tables);
+    for (spin_handle *h : b->reps)
+        spin_destroy(h);
+    if (b->own_stream && b->stream)
+        (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+// Tile list for one tile shape: replicas with more tiles first (they bound
+// the half-sweep's duration), each replica's tiles contiguous.
+int build_tiles(spin_batch *b, int rows)
+{
+    const int k = shape_index(rows);
+    const size_t n = b->reps.size();
+    std::vector<uint64_t> tiles(n);
+    for (size_t r = 0; r < n; ++r)
+        tiles[r] = spin::sweep_tiles(b->reps[r]->lat, rows);
+    std::vector<uint32_t> order(n);
+    for (size_t r = 0; r < n; ++r)
+        order[r] = (uint32_t)r;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t c) { return tiles[a] > tiles[c]; });
+    std::vector<spin::BatchReplica> host(n);
+    std::vector<uint32_t> tile_rep;
+    uint64_t next = 0;
+    for (uint32_t r : order) {
+        host[r].lat = b->reps[r]->lat;
+        host[r].sched = b->table_of[r];
+        host[r].tile0 = next;
+        for (uint64_t q = 0; q < tiles[r]; ++q)
+            tile_rep.push_back(r);
+        next += tiles[r];
+    }
+    b->ntiles[k] = next;
+    HIP_TRY(hipMalloc(&b->d_reps[k], n * sizeof(spin::BatchReplica)), "hipMalloc");
+    HIP_TRY(hipMalloc(&b->d_tile_rep[k], tile_rep.size() * sizeof(uint32_t)), "hipMalloc");
+    HIP_TRY(hipMemcpy(b->d_reps[k], host.data(), n * sizeof(spin::BatchReplica), hipMemcpyHostToDevice),
+            "hipMemcpy");
+    HIP_TRY(hipMemcpy(b->d_tile_rep[k], tile_rep.data(), tile_rep.size() * sizeof(uint32_t),
+                      hipMemcpyHostToDevice),
+            "hipMemcpy");
+    return 0;
+}
+
+int launch_sweeps(spin_batch *b, int rows, uint64_t t0, uint32_t n, hipStream_t st)
+{
+    const int k = shape_index(rows);
+    for (uint32_t q = 0; q < n; ++q) {
+        const uint64_t step = t0 + q;
+        for (uint32_t c = 0; c < 2; ++c)
+            HIP_TRY(spin::launch_batch_half_sweep(rows, b->d_reps[k], b->d_tile_rep[k], b->ntiles[k], b->d_tables,
+                                                  b->n_steps, (uint32_t)step, (uint32_t)step, c, st),
+                    "batched sweep launch");
+    }
+    return 0;
+}
+
+// Choose the tile shape: copy every lattice to scratch memory, time two
+// sweeps of each shape on the copies with HIP events, keep the faster.
+int autotune(spin_batch *b)
+{
+    size_t total = 0;
+    for (spin_handle *h : b->reps)
+        total += (h->buf_bytes + 255) / 256 * 256;
+    char *scratch = nullptr;
+    if (hipMalloc(&scratch, total) != hipSuccess) {
+        (void)hipGetLastError();
+        b->rows = 8;  // no room to tune: keep the default shape
+        return 0;
+    }
+    std::vector<spin::Lattice> saved;
+    size_t off = 0;
+    for (spin_handle *h : b->reps) {
+        saved.push_back(h->lat);
+        HIP_TRY(hipMemcpyAsync(scratch + off, h->buf, h->buf_bytes, hipMemcpyDeviceToDevice, b->stream),
+                "hipMemcpyAsync");
+        off += (h->buf_bytes + 255) / 256 * 256;
+    }
+    // descriptor copies pointing at the scratch lattices
+    float best_ms = 0.0f;
+    int best = 8;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+    for (int rows : spin::kBatchRowChoices) {
+        const int k = shape_index(rows);
+        std::vector<spin::BatchReplica> host(b->reps.size());
+        HIP_TRY(hipMemcpy(host.data(), b->d_reps[k], host.size() * sizeof(spin::BatchReplica),
+                          hipMemcpyDeviceToHost),
+                "hipMemcpy");
+        size_t o = 0;
+        for (size_t r = 0; r < host.size(); ++r) {
+            host[r].lat.planes = (uint32_t *)(scratch + o);
+            o += (b->reps[r]->buf_bytes + 255) / 256 * 256;
+        }
+        spin::BatchReplica *d_tmp = nullptr;
+        HIP_TRY(hipMalloc(&d_tmp, host.size() * sizeof(spin::BatchReplica)), "hipMalloc");
+        HIP_TRY(hipMemcpy(d_tmp, host.data(), host.size() * sizeof(spin::BatchReplica), hipMemcpyHostToDevice),
+                "hipMemcpy");
+        spin::BatchReplica *keep = b->d_reps[k];
+        b->d_reps[k] = d_tmp;
+        int rc = launch_sweeps(b, rows, b->t, 1, b->stream);  // warm-up
+        if (!rc) {
+            HIP_TRY(hipEventRecord(e0, b->stream), "hipEventRecord");
+            rc = launch_sweeps(b, rows, b->t, 2, b->stream);
+            HIP_TRY(hipEventRecord(e1, b->stream), "hipEventRecord");
+            HIP_TRY(hipEventSynchronize(e1), "hipEventSynchronize");
+        }
+        b->d_reps[k] = keep;
+        (void)hipFree(d_tmp);
+        if (rc)
+            return rc;
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        if (best_ms == 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = rows;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    (void)hipFree(scratch);
+    b->rows = best;
+    return 0;
+}
+
+} // namespace
+
+extern "C" {
+
+int spin_batch_create(uint32_t n, const spin_replica_desc *descs, uint32_t n_sched, uint32_t n_steps,
+                      const double *T, void *hip_stream, spin_batch **out)
+{
+    if (!out)
+        return fail(-EINVAL, "NULL output pointer");
+    *out = nullptr;
+    if (n == 0 || !descs || n_sched == 0 || n_steps == 0 || !T)
+        return fail(-EINVAL, "empty batch or schedule");
+    if (n_steps > (1u << 31))
+        return fail(-EINVAL, "schedule too long");
+    for (uint64_t q = 0; q < (uint64_t)n_sched * n_steps; ++q)
+        if (!(T[q] >= 0.0))
+            return fail(-EINVAL, "schedule temperature %llu is negative or NaN", (unsigned long long)q);
+    spin_batch *b = new (std::nothrow) spin_batch;
+    if (!b)
+        return fail(-ENOMEM, "out of host memory");
+    b->n_steps = n_steps;
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete b;
+            return hip_fail(e, "hipStreamCreateWithFlags");
+        }
+        b->own_stream = true;
+    }
+    // one threshold table per distinct (model, J, Delta, schedule)
+    std::map<std::tuple<int, double, double, uint32_t>, uint32_t> ids;
+    for (uint32_t r = 0; r < n; ++r) {
+        const spin_replica_desc &d = descs[r];
+        if (d.schedule >= n_sched) {
+            release(b);
+            return fail(-EINVAL, "replica %u: schedule %u out of range", r, d.schedule);
+        }
+        spin_handle *h = nullptr;
+        int rc = spin_create(d.model, d.L, d.seed, d.J, d.Delta, d.dev_buf, d.buf_bytes, b->stream, &h);
+        if (rc) {
+            std::string msg = spin_last_error();
+            release(b);
+            return fail(rc, "replica %u: %s", r, msg.c_str());
+        }
+        b->reps.push_back(h);
+        auto key = std::make_tuple(d.model, d.J, d.Delta, d.schedule);
+        auto it = ids.find(key);
+        if (it == ids.end())
+            it = ids.emplace(key, (uint32_t)ids.size()).first;
+        b->table_of.push_back(it->second);
+    }
+    b->n_tables = (uint32_t)ids.size();
+    std::vector<GroupTable> tables((size_t)b->n_tables * n_steps);
+    for (const auto &kv : ids) {
+        const int model = std::get<0>(kv.first);
+        const double J = std::get<1>(kv.first), Delta = std::get<2>(kv.first);
+        const uint32_t s = std::get<3>(kv.first);
+        for (uint32_t k = 0; k < n_steps; ++k) {
+            const double Tk = T[(size_t)s * n_steps + k];
+            if (k > 0 && Tk == T[(size_t)s * n_steps + k - 1])
+                tables[(size_t)kv.second * n_steps + k] = tables[(size_t)kv.second * n_steps + k - 1];
+            else
+                tables[(size_t)kv.second * n_steps + k] = make_groups(model, J, Delta, Tk);
+        }
+    }
+    hipError_t e = hipMalloc(&b->d_tables, tables.size() * sizeof(GroupTable));
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_tables, tables.data(), tables.size() * sizeof(GroupTable), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        release(b);
+        return hip_fail(e, "threshold tables");
+    }
+    for (int rows : spin::kBatchRowChoices) {
+        int rc = build_tiles(b, rows);
+        if (rc) {
+            std::string msg = spin_last_error();
+            release(b);
+            return fail(rc, "%s", msg.c_str());
+        }
+    }
+    *out = b;
+    return 0;
+}
+
+int spin_batch_init_random(spin_batch *b)
+{
+    if (!b)
+        return fail(-EINVAL, "NULL batch");
+    for (spin_handle *h : b->reps)
+        if (int rc = spin_init_random(h))
+            return rc;
+    return 0;
+}
+
+int spin_batch_run(spin_batch *b, uint32_t n, uint32_t flags)
+{
+    if (!b)
+        return fail(-EINVAL, "NULL batch");
+    if (flags & ~(SPIN_BATCH_DIRECT | SPIN_BATCH_ROWS4 | SPIN_BATCH_ROWS8))
+        return fail(-EINVAL, "unknown flags 0x%x", flags);
+    if (b->t + n > b->n_steps)
+        return fail(-EINVAL, "schedule has %u steps, %llu done, %u asked", b->n_steps, (unsigned long long)b->t, n);
+    if (n == 0)
+        return 0;
+    if (flags & SPIN_BATCH_ROWS4)
+        b->rows = 4;
+    else if (flags & SPIN_BATCH_ROWS8)
+        b->rows = 8;
+    else if (b->rows == 0) {
+        if (int rc = autotune(b))
+            return rc;
+    }
+    if (flags & SPIN_BATCH_DIRECT) {
+        if (int rc = launch_sweeps(b, b->rows, b->t, n, b->stream))
+            return rc;
+    } else {
+        HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+        if (b->exec) {
+            (void)hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
+        }
+        if (b->graph) {
+            (void)hipGraphDestroy(b->graph);
+            b->graph = nullptr;
+        }
+        HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        int rc = launch_sweeps(b, b->rows, b->t, n, b->stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(b->stream, &g);
+        if (rc) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess)
+            return hip_fail(e, "hipStreamEndCapture");
+        b->graph = g;
+        HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        HIP_TRY(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
+    }
+    b->t += n;
+    for (spin_handle *h : b->reps) {
+        h->t = b->t;
+        h->em_valid = false;
+    }
+    return 0;
+}
+
+int spin_batch_sync(spin_batch *b)
+{
+    if (!b)
+        return fail(-EINVAL, "NULL batch");
+    HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    return 0;
+}
+
+int spin_batch_replica(spin_batch *b, uint32_t k, spin_handle **out)
+{
+    if (!b || !out || k >= b->reps.size())
+        return fail(-EINVAL, "bad batch, output or replica index");
+    *out = b->reps[k];
+    return 0;
+}
+
+int spin_batch_info(const spin_batch *b, uint32_t *n_replicas, uint64_t *t, int *rows, uint64_t *tiles)
+{
+    if (!b)
+        return fail(-EINVAL, "NULL batch");
+    if (n_replicas)
+        *n_replicas = (uint32_t)b->reps.size();
+    if (t)
+        *t = b->t;
+    if (rows)
+        *rows = b->rows;
+    if (tiles)
+        *tiles = b->rows ? b->ntiles[shape_index(b->rows)] : 0;
+    return 0;
+}
+
+int spin_batch_destroy(spin_batch *b)
+{
+    release(b);
+    return 0;
+}
+
+} // extern "C"

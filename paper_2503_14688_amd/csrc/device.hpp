@@ -81,6 +81,26 @@ __device__ __forceinline__ uint32_t stream_tag(uint32_t purpose, uint32_t colour
 //
 // need[g]: sites whose move needs a random number and whose threshold is
 // thr[g]; always: sites accepted outright.  Returns the accepted sites.
+//
+// apply_block consumes the four planes of block blk; metropolis_accept runs
+// the whole lazy test for one word.
+template <int NG>
+__device__ __forceinline__ void apply_block(const Block4 &r, uint32_t blk, const uint32_t (&need)[NG],
+                                            const uint32_t (&thr)[NG], uint32_t &undecided, uint32_t &accepted)
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t shift = 31u - (4u * blk + (uint32_t)q);
+        uint32_t tb = 0;
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+            tb |= need[g] & (0u - ((thr[g] >> shift) & 1u));
+        const uint32_t ub = r.v[q];
+        accepted |= undecided & tb & ~ub;
+        undecided &= ~(tb ^ ub);
+    }
+}
+
 template <int NG>
 __device__ __forceinline__ uint32_t metropolis_accept(const uint32_t (&need)[NG], const uint32_t (&thr)[NG],
                                                       uint32_t always, uint32_t row, uint32_t word,
@@ -93,19 +113,29 @@ __device__ __forceinline__ uint32_t metropolis_accept(const uint32_t (&need)[NG]
     uint32_t accepted = always;
     for (uint32_t blk = 0; blk < 8u && undecided != 0u; ++blk) {
         const Block4 r = philox4x32_10(row, word, t, stream_tag(kPurposeAccept, colour, blk), k0, k1);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t shift = 31u - (4u * blk + (uint32_t)q);
-            uint32_t tb = 0;
-#pragma unroll
-            for (int g = 0; g < NG; ++g)
-                tb |= need[g] & (0u - ((thr[g] >> shift) & 1u));
-            const uint32_t ub = r.v[q];
-            accepted |= undecided & tb & ~ub;
-            undecided &= ~(tb ^ ub);
-        }
+        apply_block<NG>(r, blk, need, thr, undecided, accepted);
     }
     return accepted;
+}
+
+// Append slot to an LDS queue for every lane where pred holds: one LDS atomic
+// per wavefront, positions from the lane's rank among the set ballot bits.
+__device__ __forceinline__ void wave_enqueue(bool pred, uint32_t slot, uint16_t *queue, int *count)
+{
+    const unsigned long long mask = __ballot(pred);
+    if (mask == 0)
+        return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll(mask) - 1;
+    int base = 0;
+    if (lane == leader)
+        base = atomicAdd(count, __popcll(mask));
+    base = __shfl(base, leader, 64);
+    if (pred) {
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+        queue[base + (int)rank] = (uint16_t)slot;
+    }
 }
 
 // Full adder and half adder on bit-sliced operands.

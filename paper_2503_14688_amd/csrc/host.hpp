@@ -1,0 +1,48 @@
+// Host-side internals shared by the C ABI translation units (not public).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/spin.h"
+#include "kernels.hpp"
+
+using spin::GroupTable;
+
+struct spin_handle {
+    spin::Lattice lat;
+    int model;
+    uint32_t L;
+    uint64_t seed;
+    double J, Delta;
+    void *buf;
+    size_t buf_bytes;
+    hipStream_t stream;
+    uint64_t t;
+    unsigned long long *d_acc;  // [4 EM counters | corr counters]
+    size_t acc_cap;             // entries
+    int8_t *d_win;
+    size_t win_cap;             // bytes
+    bool em_valid;              // d_acc[0..3] describe the current state
+};
+
+namespace spin_host {
+
+// Record a failure for spin_last_error() and return code.
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+// Acceptance-group table of a model at bath temperature T (host FP64 exp).
+GroupTable make_groups(int model, double J, double Delta, double T);
+int ensure_acc(spin_handle *h, size_t entries);
+
+} // namespace spin_host
+
+#define HIP_TRY(expr, what)                                                                                  \
+    do {                                                                                                     \
+        hipError_t e_ = (expr);                                                                              \
+        if (e_ != hipSuccess)                                                                                \
+            return spin_host::hip_fail(e_, what);                                                            \
+    } while (0)

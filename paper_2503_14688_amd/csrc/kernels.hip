@@ -18,6 +18,21 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kRows = 8;  // rows walked by one thread (vertical register reuse)
 
+// Blocks of a persistent kernel that are resident at once on the current
+// device (occupancy x compute units), so a grid-stride loop has no tail wave.
+template <typename K>
+unsigned resident_grid(K kernel, size_t dyn_lds, uint64_t tiles)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kernel, kBlock, dyn_lds);
+    uint64_t g = (uint64_t)(cus > 0 ? cus : 256) * (uint64_t)(per_cu > 0 ? per_cu : 1);
+    if (g > tiles)
+        g = tiles;
+    return (unsigned)(g ? g : 1);
+}
+
 inline unsigned grid_for(uint64_t items)
 {
     uint64_t b = (items + kBlock - 1) / kBlock;
@@ -89,65 +104,158 @@ __global__ __launch_bounds__(kBlock) void k_init_bc(uint32_t *planes, uint32_t L
     }
 }
 
-// -------------------------------------------------------- Ising sweep --
+// ------------------------------------------------------------ sweeps --
+//
+// Work unit: a tile of kBlock items; with R rows per thread, item g of a
+// lattice is word column w = g mod W over the R rows starting at R (g / W),
+// and thread tid of a block takes item tile * kBlock + tid.  Single-lattice kernels walk the
+// tiles of one lattice; the batched kernel walks a flat list of the tiles of
+// many lattices.
 
-template <bool MEASURE>
-__global__ __launch_bounds__(kBlock) void k_sweep_ising(Lattice lat, uint32_t c, uint32_t t, GroupTable gt,
-                                                        unsigned long long *acc)
+// Ising half-sweep with a block-wide work queue for the random planes.
+// Phase 1: every word gets its classes and the first Philox block (planes
+// 0-3), which settles most sites.  Words with sites still undecided go to an
+// LDS queue; each later round hands one queued word per thread the next
+// block, so a Philox call is spent only where a site still needs a plane (a
+// per-word loop makes the whole wavefront wait for its slowest word).  Phase
+// 3 writes the words back.  Every site ends with the outcome that all 32
+// planes define.
+template <int R>
+struct IsingQueue {
+    static constexpr int kSlots = R * kBlock;
+    uint32_t U[kSlots], A[kSlots], m3[kSlots], m4[kSlots];
+    uint16_t q[2][kSlots];
+    uint32_t i0[kBlock], w[kBlock];
+    int count[2];
+};
+
+struct IsingNbrs {
+    uint32_t up, dn, cur, side;
+};
+
+__device__ __forceinline__ IsingNbrs ising_nbrs(const uint32_t *oth, uint32_t L, uint32_t W, uint32_t c,
+                                                uint32_t i, uint32_t w)
+{
+    const uint32_t iu = i == 0 ? L - 1 : i - 1, id = i + 1 == L ? 0 : i + 1;
+    const uint32_t odd = (i + c) & 1u;
+    const uint32_t wn = odd ? (w + 1u == W ? 0u : w + 1u) : (w == 0 ? W : w) - 1u;
+    IsingNbrs n;
+    n.up = oth[(size_t)iu * W + w];
+    n.dn = oth[(size_t)id * W + w];
+    n.cur = oth[(size_t)i * W + w];
+    n.side = side_word(n.cur, oth[(size_t)i * W + wn], odd);
+    return n;
+}
+
+template <bool MEASURE, int R>
+__device__ __forceinline__ void ising_tile(const Lattice &lat, uint32_t c, uint32_t t, const GroupTable &gt,
+                                           uint64_t tile, IsingQueue<R> &Q, unsigned long long (&e)[kEmCounters])
 {
     const uint32_t L = lat.L, W = lat.W;
     uint32_t *own = lat.planes + (c ? lat.plane_u32 : 0);
     const uint32_t *oth = lat.planes + (c ? 0 : lat.plane_u32);
-    const uint64_t nitems = (uint64_t)(L / kRows) * W;
+    const uint64_t nitems = (uint64_t)(L / R) * W;
     const uint32_t thr[2] = {gt.thr[0], gt.thr[1]};
     const bool rng3 = gt.rng_bits & 1u, rng4 = gt.rng_bits & 2u;
     const bool nev3 = gt.never_bits & 1u, nev4 = gt.never_bits & 2u;
-    unsigned long long e[kEmCounters] = {0, 0, 0, 0};
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nitems;
-         g += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t rg = (uint32_t)(g / W);
-        const uint32_t w = (uint32_t)(g - (uint64_t)rg * W);
-        const uint32_t i0 = rg * kRows;
+    const uint32_t k0 = lat.key0, k1 = lat.key1;
+    const uint32_t tid = threadIdx.x;
+    const uint64_t g = tile * kBlock + tid;
+    const bool valid = g < nitems;
+    const uint32_t rg = valid ? (uint32_t)(g / W) : 0u;
+    const uint32_t w = valid ? (uint32_t)(g - (uint64_t)rg * W) : 0u;
+    const uint32_t i0 = rg * R;
+    Q.i0[tid] = i0;
+    Q.w[tid] = w;
+    if (tid == 0)
+        Q.count[0] = 0;
+    __syncthreads();
+    uint32_t s[R], A[R];
+    uint32_t queued = 0;
+    if (valid) {
         const uint32_t wl = (w == 0 ? W : w) - 1u;
         const uint32_t wr = (w + 1u == W) ? 0u : w + 1u;
         uint32_t up = oth[(size_t)(i0 == 0 ? L - 1 : i0 - 1) * W + w];
         uint32_t cur = oth[(size_t)i0 * W + w];
 #pragma unroll
-        for (int r = 0; r < kRows; ++r) {
+        for (int r = 0; r < R; ++r) {
             const uint32_t i = i0 + (uint32_t)r;
             const uint32_t inext = (i + 1u == L) ? 0u : i + 1u;
             const uint32_t dn = oth[(size_t)inext * W + w];
             const uint32_t odd = (i + c) & 1u;
-            const uint32_t nb = oth[(size_t)i * W + (odd ? wr : wl)];
-            const uint32_t side = side_word(cur, nb, odd);
-            const size_t idx = (size_t)i * W + w;
-            const uint32_t s = own[idx];
+            const uint32_t side = side_word(cur, oth[(size_t)i * W + (odd ? wr : wl)], odd);
+            const uint32_t sv = own[(size_t)i * W + w];
             // aligned-neighbour indicators; a = number aligned, dE = J (4a - 8)
-            const uint32_t e1 = ~(s ^ up), e2 = ~(s ^ dn), e3 = ~(s ^ cur), e4 = ~(s ^ side);
+            const uint32_t e1 = ~(sv ^ up), e2 = ~(sv ^ dn), e3 = ~(sv ^ cur), e4 = ~(sv ^ side);
             const uint32_t a1 = e1 & e2, x1 = e1 ^ e2, a2 = e3 & e4, x2 = e3 ^ e4;
             const uint32_t m4 = a1 & a2;                // a = 4: dE = 8J
             const uint32_t m3 = (a1 & x2) | (a2 & x1);  // a = 3: dE = 4J
             const uint32_t need[2] = {rng3 ? m3 : 0u, rng4 ? m4 : 0u};
             const uint32_t never = (nev3 ? m3 : 0u) | (nev4 ? m4 : 0u);
-            const uint32_t always = ~(need[0] | need[1] | never);
-            const uint32_t flip = metropolis_accept<2>(need, thr, always, i, w, t, c, lat.key0, lat.key1);
-            const uint32_t ns = s ^ flip;
-            own[idx] = ns;
-            if (MEASURE) {
-                e[0] += 64;
-                e[1] += __popc(ns) + __popc(cur);
-                e[2] += 128;
-                e[3] += __popc(ns ^ up) + __popc(ns ^ dn) + __popc(ns ^ cur) + __popc(ns ^ side);
+            uint32_t acc_mask = ~(need[0] | need[1] | never);
+            uint32_t und = need[0] | need[1];
+            if (und != 0u) {
+                const Block4 b = philox4x32_10(i, w, t, stream_tag(kPurposeAccept, c, 0), k0, k1);
+                apply_block<2>(b, 0u, need, thr, und, acc_mask);
             }
+            s[r] = sv;
+            A[r] = acc_mask;
+            const uint32_t slot = (uint32_t)r * kBlock + tid;
+            if (und != 0u) {
+                Q.U[slot] = und;
+                Q.A[slot] = acc_mask;
+                Q.m3[slot] = need[0];
+                Q.m4[slot] = need[1];
+                queued |= 1u << r;
+            }
+            wave_enqueue(und != 0u, slot, Q.q[0], &Q.count[0]);
             up = cur;
             cur = dn;
         }
     }
-    if (MEASURE)
-        block_reduce_atomic<kEmCounters>(e, acc);
+    __syncthreads();
+    int cq = 0;
+    for (uint32_t blk = 1; blk < 8u; ++blk) {
+        const int n = Q.count[cq];
+        if (n == 0)
+            break;
+        if (tid == 0)
+            Q.count[cq ^ 1] = 0;
+        __syncthreads();
+        for (int k = (int)tid; k < n; k += kBlock) {
+            const uint32_t slot = Q.q[cq][k];
+            const uint32_t owner = slot % kBlock;
+            const uint32_t i = Q.i0[owner] + slot / kBlock;
+            const uint32_t need[2] = {Q.m3[slot], Q.m4[slot]};
+            uint32_t und = Q.U[slot], acc_mask = Q.A[slot];
+            const Block4 b = philox4x32_10(i, Q.w[owner], t, stream_tag(kPurposeAccept, c, blk), k0, k1);
+            apply_block<2>(b, blk, need, thr, und, acc_mask);
+            Q.U[slot] = und;
+            Q.A[slot] = acc_mask;
+            wave_enqueue(und != 0u, slot, Q.q[cq ^ 1], &Q.count[cq ^ 1]);
+        }
+        __syncthreads();
+        cq ^= 1;
+    }
+    if (valid) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t i = i0 + (uint32_t)r;
+            // sites still tied after 32 planes have u == thr: rejected
+            const uint32_t flip = ((queued >> r) & 1u) ? Q.A[(uint32_t)r * kBlock + tid] : A[r];
+            const uint32_t ns = s[r] ^ flip;
+            own[(size_t)i * W + w] = ns;
+            if (MEASURE) {
+                const IsingNbrs nb = ising_nbrs(oth, L, W, c, i, w);
+                e[0] += 64;
+                e[1] += __popc(ns) + __popc(nb.cur);
+                e[2] += 128;
+                e[3] += __popc(ns ^ nb.up) + __popc(ns ^ nb.dn) + __popc(ns ^ nb.cur) + __popc(ns ^ nb.side);
+            }
+        }
+    }
+    __syncthreads();
 }
-
-// -------------------------------------------------- Blume-Capel sweep --
 
 struct Pair {
     uint32_t z, s;  // z: s != 0, s: s < 0
@@ -159,100 +267,154 @@ __device__ __forceinline__ Pair load_pair(const uint32_t *plane, size_t word)
     return Pair{v.x, v.y};
 }
 
-template <bool MEASURE>
-__global__ __launch_bounds__(kBlock) void k_sweep_bc(Lattice lat, uint32_t c, uint32_t t, GroupTable gt,
-                                                     unsigned long long *acc)
+// Blume-Capel half-sweep of one tile: per word the proposal plane, the
+// bit-sliced y = s_eff * h (neighbour sum seen from the sign that the move
+// carries), the 13 acceptance groups and the lazy Metropolis test.
+template <bool MEASURE, int R>
+__device__ __forceinline__ void bc_tile(const Lattice &lat, uint32_t c, uint32_t t, const GroupTable &gt,
+                                        uint64_t tile, unsigned long long (&e)[kEmCounters])
 {
     const uint32_t L = lat.L, W = lat.W;
     uint32_t *own = lat.planes + (c ? lat.plane_u32 : 0);
     const uint32_t *oth = lat.planes + (c ? 0 : lat.plane_u32);
-    const uint64_t nitems = (uint64_t)(L / kRows) * W;
+    const uint64_t nitems = (uint64_t)(L / R) * W;
+    const uint64_t g = tile * kBlock + threadIdx.x;
+    if (g >= nitems)
+        return;
     uint32_t thr[kBcGroups];
 #pragma unroll
-    for (int g = 0; g < kBcGroups; ++g)
-        thr[g] = gt.thr[g];
-    unsigned long long e[kEmCounters] = {0, 0, 0, 0};
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nitems;
-         g += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t rg = (uint32_t)(g / W);
-        const uint32_t w = (uint32_t)(g - (uint64_t)rg * W);
-        const uint32_t i0 = rg * kRows;
-        const uint32_t wl = (w == 0 ? W : w) - 1u;
-        const uint32_t wr = (w + 1u == W) ? 0u : w + 1u;
-        Pair up = load_pair(oth, (size_t)(i0 == 0 ? L - 1 : i0 - 1) * W + w);
-        Pair cur = load_pair(oth, (size_t)i0 * W + w);
+    for (int q = 0; q < kBcGroups; ++q)
+        thr[q] = gt.thr[q];
+    const uint32_t rg = (uint32_t)(g / W);
+    const uint32_t w = (uint32_t)(g - (uint64_t)rg * W);
+    const uint32_t i0 = rg * R;
+    const uint32_t wl = (w == 0 ? W : w) - 1u;
+    const uint32_t wr = (w + 1u == W) ? 0u : w + 1u;
+    Pair up = load_pair(oth, (size_t)(i0 == 0 ? L - 1 : i0 - 1) * W + w);
+    Pair cur = load_pair(oth, (size_t)i0 * W + w);
 #pragma unroll 2
-        for (int r = 0; r < kRows; ++r) {
-            const uint32_t i = i0 + (uint32_t)r;
-            const uint32_t inext = (i + 1u == L) ? 0u : i + 1u;
-            const Pair dn = load_pair(oth, (size_t)inext * W + w);
-            const uint32_t odd = (i + c) & 1u;
-            const Pair nbw = load_pair(oth, (size_t)i * W + (odd ? wr : wl));
-            const Pair side{side_word(cur.z, nbw.z, odd), side_word(cur.s, nbw.s, odd)};
-            const size_t idx = (size_t)i * W + w;
-            const Pair s = load_pair(own, idx);
-            // proposal bit per site: plane 0 of the proposal stream
-            const uint32_t X = philox4x32_10(i, w, t, stream_tag(kPurposePropose, c, 0), lat.key0, lat.key1).v[0];
-            // sign carried by y: that of s when s != 0, of the proposed s' when s = 0
-            const uint32_t neg = (s.z & s.s) | (~s.z & X);
-            const Pair nbr[4] = {up, dn, cur, side};
-            uint32_t bits[8];
+    for (int r = 0; r < R; ++r) {
+        const uint32_t i = i0 + (uint32_t)r;
+        const uint32_t inext = (i + 1u == L) ? 0u : i + 1u;
+        const Pair dn = load_pair(oth, (size_t)inext * W + w);
+        const uint32_t odd = (i + c) & 1u;
+        const Pair nbw = load_pair(oth, (size_t)i * W + (odd ? wr : wl));
+        const Pair side{side_word(cur.z, nbw.z, odd), side_word(cur.s, nbw.s, odd)};
+        const size_t idx = (size_t)i * W + w;
+        const Pair s = load_pair(own, idx);
+        // proposal bit per site: plane 0 of the proposal stream
+        const uint32_t X = philox4x32_10(i, w, t, stream_tag(kPurposePropose, c, 0), lat.key0, lat.key1).v[0];
+        // sign carried by y: that of s when s != 0, of the proposed s' when s = 0
+        const uint32_t neg = (s.z & s.s) | (~s.z & X);
+        const Pair nbr[4] = {up, dn, cur, side};
+        uint32_t bits[8];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const uint32_t anti = nbr[n].s ^ neg;
+            bits[n] = nbr[n].z & ~anti;        // neighbour contributes +1 to y
+            bits[4 + n] = ~(nbr[n].z & anti);  // neighbour does not contribute -1
+        }
+        uint32_t b0, b1, b2, b3;
+        count8(bits, b0, b1, b2, b3);  // v = y + 4 in [0, 8]
+        uint32_t Y[9];
+        {
+            const uint32_t nb3 = ~b3;
+            const uint32_t t0 = ~b1 & ~b0, t1 = ~b1 & b0, t2 = b1 & ~b0, t3 = b1 & b0;
+            const uint32_t h0 = nb3 & ~b2, h1 = nb3 & b2;
+            Y[0] = h0 & t0; Y[1] = h0 & t1; Y[2] = h0 & t2; Y[3] = h0 & t3;
+            Y[4] = h1 & t0; Y[5] = h1 & t1; Y[6] = h1 & t2; Y[7] = h1 & t3;
+            Y[8] = b3;
+        }
+        const uint32_t famA = s.z & ~X;  // s -> 0:   dE = J y - Delta
+        const uint32_t famB = ~s.z;      // 0 -> s':  dE = -J y + Delta
+        const uint32_t famC = s.z & X;   // s -> -s:  dE = 2 J y
+        uint32_t need[kBcGroups];
+        uint32_t never = 0, any = 0;
+#pragma unroll
+        for (int q = 0; q < kBcGroups; ++q) {
+            const uint32_t mask = q < 9 ? ((((gt.sel_a_bits >> q) & 1u) ? famA : famB) & Y[q])
+                                        : (famC & Y[q - 4]);
+            need[q] = ((gt.rng_bits >> q) & 1u) ? mask : 0u;
+            never |= ((gt.never_bits >> q) & 1u) ? mask : 0u;
+            any |= need[q];
+        }
+        const uint32_t always = ~(any | never);
+        const uint32_t F = metropolis_accept<kBcGroups>(need, thr, always, i, w, t, c, lat.key0, lat.key1);
+        const uint32_t zp = ~s.z | X;          // proposed s' != 0
+        const uint32_t sp = X & ~(s.z & s.s);  // proposed s' < 0
+        const uint32_t nz = (F & zp) | (~F & s.z);
+        const uint32_t ns = (F & sp) | (~F & s.s);
+        uint2 out;
+        out.x = nz;
+        out.y = ns;
+        reinterpret_cast<uint2 *>(own)[idx] = out;
+        if (MEASURE) {
+            e[0] += __popc(nz) + __popc(cur.z);
+            e[1] += __popc(ns) + __popc(cur.s);
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
-                const uint32_t anti = nbr[n].s ^ neg;
-                bits[n] = nbr[n].z & ~anti;        // neighbour contributes +1 to y
-                bits[4 + n] = ~(nbr[n].z & anti);  // neighbour does not contribute -1
+                const uint32_t both = nz & nbr[n].z;
+                e[2] += __popc(both);
+                e[3] += __popc(both & (ns ^ nbr[n].s));
             }
-            uint32_t b0, b1, b2, b3;
-            count8(bits, b0, b1, b2, b3);  // v = y + 4 in [0, 8]
-            uint32_t Y[9];
-            {
-                const uint32_t nb3 = ~b3;
-                const uint32_t t0 = ~b1 & ~b0, t1 = ~b1 & b0, t2 = b1 & ~b0, t3 = b1 & b0;
-                const uint32_t h0 = nb3 & ~b2, h1 = nb3 & b2;
-                Y[0] = h0 & t0; Y[1] = h0 & t1; Y[2] = h0 & t2; Y[3] = h0 & t3;
-                Y[4] = h1 & t0; Y[5] = h1 & t1; Y[6] = h1 & t2; Y[7] = h1 & t3;
-                Y[8] = b3;
-            }
-            const uint32_t famA = s.z & ~X;  // s -> 0:   dE = J y - Delta
-            const uint32_t famB = ~s.z;      // 0 -> s':  dE = -J y + Delta
-            const uint32_t famC = s.z & X;   // s -> -s:  dE = 2 J y
-            uint32_t need[kBcGroups];
-            uint32_t never = 0, any = 0;
-#pragma unroll
-            for (int q = 0; q < kBcGroups; ++q) {
-                const uint32_t mask = q < 9 ? ((((gt.sel_a_bits >> q) & 1u) ? famA : famB) & Y[q])
-                                            : (famC & Y[q - 4]);
-                need[q] = ((gt.rng_bits >> q) & 1u) ? mask : 0u;
-                never |= ((gt.never_bits >> q) & 1u) ? mask : 0u;
-                any |= need[q];
-            }
-            const uint32_t always = ~(any | never);
-            const uint32_t F = metropolis_accept<kBcGroups>(need, thr, always, i, w, t, c, lat.key0, lat.key1);
-            const uint32_t zp = ~s.z | X;          // proposed s' != 0
-            const uint32_t sp = X & ~(s.z & s.s);  // proposed s' < 0
-            const uint32_t nz = (F & zp) | (~F & s.z);
-            const uint32_t ns = (F & sp) | (~F & s.s);
-            uint2 out;
-            out.x = nz;
-            out.y = ns;
-            reinterpret_cast<uint2 *>(own)[idx] = out;
-            if (MEASURE) {
-                e[0] += __popc(nz) + __popc(cur.z);
-                e[1] += __popc(ns) + __popc(cur.s);
-#pragma unroll
-                for (int n = 0; n < 4; ++n) {
-                    const uint32_t both = nz & nbr[n].z;
-                    e[2] += __popc(both);
-                    e[3] += __popc(both & (ns ^ nbr[n].s));
-                }
-            }
-            up = cur;
-            cur = dn;
         }
+        up = cur;
+        cur = dn;
     }
+}
+
+template <int R>
+__host__ __device__ inline uint64_t tiles_of(const Lattice &lat)
+{
+    return ((uint64_t)(lat.L / R) * lat.W + kBlock - 1) / kBlock;
+}
+
+template <bool MEASURE>
+__global__ __launch_bounds__(kBlock) void k_sweep_ising(Lattice lat, uint32_t c, uint32_t t, GroupTable gt,
+                                                        unsigned long long *acc)
+{
+    __shared__ IsingQueue<kRows> Q;
+    unsigned long long e[kEmCounters] = {0, 0, 0, 0};
+    const uint64_t ntiles = tiles_of<kRows>(lat);
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+        ising_tile<MEASURE, kRows>(lat, c, t, gt, tile, Q, e);
     if (MEASURE)
         block_reduce_atomic<kEmCounters>(e, acc);
+}
+
+template <bool MEASURE>
+__global__ __launch_bounds__(kBlock) void k_sweep_bc(Lattice lat, uint32_t c, uint32_t t, GroupTable gt,
+                                                     unsigned long long *acc)
+{
+    unsigned long long e[kEmCounters] = {0, 0, 0, 0};
+    const uint64_t ntiles = tiles_of<kRows>(lat);
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+        bc_tile<MEASURE, kRows>(lat, c, t, gt, tile, e);
+    if (MEASURE)
+        block_reduce_atomic<kEmCounters>(e, acc);
+}
+
+// Batched half-sweep: one launch advances colour c of every replica.  The
+// flat tile list maps each global tile to (replica, local tile); replica r's
+// thresholds for this sweep are tables[sched(r) * stride + step].
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica *reps, const uint32_t *tile_rep,
+                                                             uint64_t ntiles, const GroupTable *tables,
+                                                             uint32_t stride, uint32_t step, uint32_t t,
+                                                             uint32_t c)
+{
+    __shared__ IsingQueue<R> Q;
+    unsigned long long e[kEmCounters] = {0, 0, 0, 0};
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t rid = tile_rep[tile];
+        const BatchReplica &rep = reps[rid];
+        const GroupTable &gt = tables[(size_t)rep.sched * stride + step];
+        const uint64_t local = tile - rep.tile0;
+        if (rep.lat.model == kIsing)
+            ising_tile<false, R>(rep.lat, c, t, gt, local, Q, e);
+        else
+            bc_tile<false, R>(rep.lat, c, t, gt, local, e);
+    }
 }
 
 // ------------------------------------------ energy / magnetisation sums --
@@ -437,18 +599,51 @@ hipError_t launch_init(const Lattice &lat, hipStream_t st)
 hipError_t launch_half_sweep(const Lattice &lat, uint32_t colour, uint32_t t, const GroupTable &gt,
                              unsigned long long *em_acc, hipStream_t st)
 {
-    const uint64_t items = (uint64_t)(lat.L / kRows) * lat.W;
-    const dim3 grid(grid_for(items)), block(kBlock);
+    const uint64_t tiles = tiles_of<kRows>(lat);
+    const dim3 block(kBlock);
     if (lat.model == kIsing) {
-        if (em_acc)
-            hipLaunchKernelGGL(k_sweep_ising<true>, grid, block, 0, st, lat, colour, t, gt, em_acc);
-        else
-            hipLaunchKernelGGL(k_sweep_ising<false>, grid, block, 0, st, lat, colour, t, gt, em_acc);
+        if (em_acc) {
+            static const unsigned g = resident_grid(k_sweep_ising<true>, 0, ~0ull);
+            hipLaunchKernelGGL(k_sweep_ising<true>, dim3(g < tiles ? g : (unsigned)tiles), block, 0, st, lat,
+                               colour, t, gt, em_acc);
+        } else {
+            static const unsigned g = resident_grid(k_sweep_ising<false>, 0, ~0ull);
+            hipLaunchKernelGGL(k_sweep_ising<false>, dim3(g < tiles ? g : (unsigned)tiles), block, 0, st, lat,
+                               colour, t, gt, em_acc);
+        }
     } else {
-        if (em_acc)
-            hipLaunchKernelGGL(k_sweep_bc<true>, grid, block, 0, st, lat, colour, t, gt, em_acc);
-        else
-            hipLaunchKernelGGL(k_sweep_bc<false>, grid, block, 0, st, lat, colour, t, gt, em_acc);
+        if (em_acc) {
+            static const unsigned g = resident_grid(k_sweep_bc<true>, 0, ~0ull);
+            hipLaunchKernelGGL(k_sweep_bc<true>, dim3(g < tiles ? g : (unsigned)tiles), block, 0, st, lat, colour,
+                               t, gt, em_acc);
+        } else {
+            static const unsigned g = resident_grid(k_sweep_bc<false>, 0, ~0ull);
+            hipLaunchKernelGGL(k_sweep_bc<false>, dim3(g < tiles ? g : (unsigned)tiles), block, 0, st, lat,
+                               colour, t, gt, em_acc);
+        }
+    }
+    return hipGetLastError();
+}
+
+uint64_t sweep_tiles(const Lattice &lat, int rows)
+{
+    return rows == 4 ? tiles_of<4>(lat) : tiles_of<8>(lat);
+}
+
+hipError_t launch_batch_half_sweep(int rows, const BatchReplica *reps, const uint32_t *tile_rep, uint64_t ntiles,
+                                   const GroupTable *tables, uint32_t stride, uint32_t step, uint32_t t,
+                                   uint32_t colour, hipStream_t st)
+{
+    if (rows == 4) {
+        static const unsigned g = resident_grid(k_batch_half_sweep<4>, 0, ~0ull);
+        hipLaunchKernelGGL(k_batch_half_sweep<4>, dim3(g < ntiles ? g : (unsigned)ntiles), dim3(kBlock), 0, st,
+                           reps, tile_rep, ntiles, tables, stride, step, t, colour);
+    } else if (rows == 8) {
+        static const unsigned g = resident_grid(k_batch_half_sweep<8>, 0, ~0ull);
+        hipLaunchKernelGGL(k_batch_half_sweep<8>, dim3(g < ntiles ? g : (unsigned)ntiles), dim3(kBlock), 0, st,
+                           reps, tile_rep, ntiles, tables, stride, step, t, colour);
+    } else {
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -39,7 +39,23 @@ struct Lattice {
 // so sum s = acc0 - 2 acc1, sum s^2 = acc0, bond sum = acc2 - 2 acc3.
 constexpr int kEmCounters = 4;
 
+// One replica of a batch: its lattice, its schedule and its first tile in
+// the batch's flat tile list.
+struct BatchReplica {
+    Lattice lat;
+    uint32_t sched;
+    uint64_t tile0;
+};
+
 hipError_t launch_init(const Lattice &lat, hipStream_t st);
+// Sweep work units (tiles of 256 word columns x rows) of one lattice for a
+// rows-per-thread choice (4 or 8), and the batched half-sweep over a flat
+// tile list of many lattices.
+constexpr int kBatchRowChoices[2] = {4, 8};
+uint64_t sweep_tiles(const Lattice &lat, int rows);
+hipError_t launch_batch_half_sweep(int rows, const BatchReplica *reps, const uint32_t *tile_rep, uint64_t ntiles,
+                                   const GroupTable *tables, uint32_t stride, uint32_t step, uint32_t t,
+                                   uint32_t colour, hipStream_t st);
 hipError_t launch_half_sweep(const Lattice &lat, uint32_t colour, uint32_t t, const GroupTable &gt,
                              unsigned long long *em_acc, hipStream_t st);
 hipError_t launch_measure_em(const Lattice &lat, unsigned long long *em_acc, hipStream_t st);

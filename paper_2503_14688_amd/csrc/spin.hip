@@ -3,6 +3,7 @@
 // on the handle's stream, and the FP64 observables derived from the exact
 // integer sums.
 #include "../../include/spin.h"
+#include "host.hpp"
 #include "kernels.hpp"
 
 #include <cerrno>
@@ -18,26 +19,7 @@
 // derived observables are defined by plain double arithmetic.
 #pragma clang fp contract(off)
 
-using spin::GroupTable;
-
-struct spin_handle {
-    spin::Lattice lat;
-    int model;
-    uint32_t L;
-    uint64_t seed;
-    double J, Delta;
-    void *buf;
-    size_t buf_bytes;
-    hipStream_t stream;
-    uint64_t t;
-    unsigned long long *d_acc;  // [4 EM counters | corr counters]
-    size_t acc_cap;             // entries
-    int8_t *d_win;
-    size_t win_cap;             // bytes
-    bool em_valid;              // d_acc[0..3] describe the current state
-};
-
-namespace {
+namespace spin_host {
 
 thread_local std::string g_err;
 
@@ -56,13 +38,6 @@ int hip_fail(hipError_t e, const char *what)
 {
     return fail(-EIO, "%s: %s", what, hipGetErrorString(e));
 }
-
-#define HIP_TRY(expr, what)                                                                                  \
-    do {                                                                                                     \
-        hipError_t e_ = (expr);                                                                              \
-        if (e_ != hipSuccess)                                                                                \
-            return hip_fail(e_, what);                                                                       \
-    } while (0)
 
 bool valid_L(uint32_t L) { return L >= 64 && L <= (1u << 22) && (L % 64) == 0; }
 
@@ -186,7 +161,9 @@ double xi_from(const std::vector<double> &r, const std::vector<double> &C, doubl
     return I2 / I1;
 }
 
-} // namespace
+} // namespace spin_host
+
+using namespace spin_host;
 
 extern "C" {
 

@@ -1,0 +1,94 @@
+"""Batched replicas: every replica of a mixed batch (models, sizes, couplings
+and schedules) must be bit-identical to the oracle and to the same replica
+run alone, whatever the tile shape, with or without graph capture, and
+whether the sweeps come in one run or several."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_14688_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_replicas():
+    reps = []
+    sizes = [64, 128, 192, 256, 320]
+    k = 0
+    for model in (0, 1):
+        for L in sizes:
+            for Delta in ((0.0,) if model == 0 else (0.0, 0.6)):
+                reps.append(dict(model=model, L=L, seed=workloads.seed_for(k), J=1.0 if k % 3 else 0.8,
+                                 Delta=Delta, schedule=k % 3))
+                k += 1
+    return reps
+
+
+def schedules(n_steps):
+    tc = workloads.TC_ISING
+    rows = [oracle.schedule(2, [2 * tc, 1.02 * tc, 8.0], 0, n_steps),
+            oracle.schedule(1, [1.2, 5, 2.3], 0, n_steps),
+            np.linspace(3.0, 0.5, n_steps)]
+    T = np.stack(rows)
+    T[2, 4] = 0.0
+    T[1, 9] = np.inf
+    return T
+
+
+def oracle_run(rep, T_row, n):
+    s = oracle.init(rep["model"], rep["L"], rep["seed"])
+    oracle.sweep(rep["model"], s, rep["seed"], rep["J"], rep["Delta"], 0, T_row[:n])
+    return s
+
+
+@pytest.mark.parametrize("flags", [0, 4, 2, 1 | 4, 1 | 2])
+def test_batch_matches_oracle(gpu, flags):
+    reps = mixed_replicas()
+    n = 16
+    T = schedules(n)
+    b = gpu.Batch(reps, T).init_random()
+    b.run(n, flags)
+    b.sync()
+    info = b.info()
+    assert info["t"] == n and info["rows"] in (4, 8) and info["replicas"] == len(reps)
+    for k, rep in enumerate(reps):
+        assert np.array_equal(b.spins(k), oracle_run(rep, T[rep["schedule"]], n)), (k, rep)
+    b.close()
+
+
+def test_batch_chunks_and_solo_runs(gpu):
+    reps = mixed_replicas()
+    T = schedules(24)
+    a = gpu.Batch(reps, T).init_random()
+    a.run(24)
+    c = gpu.Batch(reps, T).init_random()
+    c.run(5)
+    c.run(19, gpu.BATCH_DIRECT)
+    a.sync()
+    c.sync()
+    for k, rep in enumerate(reps):
+        solo = gpu.Lattice(rep["model"], rep["L"], rep["seed"], rep["J"], rep["Delta"]).init_random()
+        solo.sweep(T[rep["schedule"]])
+        want = solo.spins()
+        assert np.array_equal(a.spins(k), want), k
+        assert np.array_equal(c.spins(k), want), k
+        ma, ms = a.measure(k, workloads.r_sparse(rep["L"])), solo.measure(workloads.r_sparse(rep["L"]))
+        assert ma["bond"] == ms["bond"] and np.array_equal(ma["Sx"], ms["Sx"]) and ma["t"] == 24
+        solo.close()
+    with pytest.raises(gpu.SpinError):
+        a.run(1)  # past the end of the schedule
+    a.close()
+    c.close()
+
+
+def test_batch_rejects_bad_descriptors(gpu):
+    reps = mixed_replicas()[:3]
+    T = schedules(4)
+    bad = [dict(r) for r in reps]
+    bad[1]["schedule"] = 7
+    with pytest.raises(gpu.SpinError):
+        gpu.Batch(bad, T)
+    T2 = T.copy()
+    T2[0, 1] = -1.0
+    with pytest.raises(gpu.SpinError):
+        gpu.Batch(reps, T2)
