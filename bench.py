@@ -60,6 +60,91 @@ def cpu_baseline(workload, budget_s=12.0):
                       f"from the T=inf start, sweeps only, {threads} OpenMP threads, {dt:.1f} s"}
 
 
+def run_batched(args):
+    """512 replicas (L in {256..2048}, half Ising half Blume-Capel, own
+    exponential schedules): the batched engine over the full schedule, and
+    batched vs the plain per-replica launch loop over the same first sweeps."""
+    import torch
+    import paper_2503_14688_amd as spin
+    from paper_2503_14688_amd import workloads
+
+    reps = workloads.batched_replicas(args.replicas)
+    n_steps = args.batch_sweeps
+    keys = sorted({(r["model"], r["tau"]) for r in reps})
+    rows = []
+    for (model, tau) in keys:
+        tc = workloads.TC_ISING if model == 0 else workloads.TC_BC
+        rows.append(spin.spin_schedule_fill(spin.SCHEDULE_EXPONENTIAL, [2.0 * tc, 1.02 * tc, tau], 0, n_steps))
+    T = np.stack(rows)
+    for r in reps:
+        r["schedule"] = keys.index((r["model"], r["tau"]))
+    flips_per_sweep = sum(r["L"] * r["L"] for r in reps)
+
+    b = spin.Batch(reps, T).init_random()
+    b.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(n_steps)
+    b.sync()
+    full_s = time.perf_counter() - t0
+    info = b.info()
+    log(f"batched: {args.replicas} replicas x {n_steps} sweeps in {full_s:.3f} s (rows per thread {info['rows']})")
+    b.close()
+
+    cmp_sweeps = min(args.compare_sweeps, n_steps)
+    b = spin.Batch(reps, T).init_random()
+    b.run(1)  # tile-shape choice and graph warm-up outside the timed range
+    b.sync()
+    b.close()
+    b = spin.Batch(reps, T).init_random()
+    b.sync()
+    t0 = time.perf_counter()
+    b.run(cmp_sweeps, spin.BATCH_ROWS8 if info["rows"] == 8 else spin.BATCH_ROWS4)
+    b.sync()
+    batched_s = time.perf_counter() - t0
+    plain = [spin.Lattice(r["model"], r["L"], r["seed"], r["J"], r["Delta"]).init_random() for r in reps]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for lat, r in zip(plain, reps):
+        lat.sweep(T[r["schedule"], :cmp_sweeps])
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    same = all(np.array_equal(b.spins(k), plain[k].spins()) for k in range(0, len(reps), max(1, len(reps) // 16)))
+    log(f"plain loop: {cmp_sweeps} sweeps in {plain_s:.3f} s vs batched {batched_s:.3f} s; identical: {same}")
+    for lat in plain:
+        lat.close()
+    b.close()
+    n = len(reps)
+    return {"workload": f"{n} replicas, L in {{256,512,1024,2048}}, half Ising half Blume-Capel, "
+                        f"T(t) = Tf + (T0 - Tf) exp(-t/tau), tau in {{64,256,1024}}",
+            "replica_sweeps_per_s": round(n * n_steps / full_s, 1), "sweeps": n_steps,
+            "flips_per_ns": round(flips_per_sweep * n_steps / full_s / 1e9, 2), "rows_per_thread": info["rows"],
+            "compare_sweeps": cmp_sweeps,
+            "batched_replica_sweeps_per_s": round(n * cmp_sweeps / batched_s, 1),
+            "plain_replica_sweeps_per_s": round(n * cmp_sweeps / plain_s, 1),
+            "ratio": round(plain_s / batched_s, 2), "identical_results": bool(same)}
+
+
+def run_serving(args, saturated_flips_per_ns):
+    """Poisson stream of quench jobs through the continuous-batching server."""
+    from paper_2503_14688_amd import workloads
+    from paper_2503_14688_amd.serve import Job, Server
+
+    mean_L2 = np.mean([4.0 ** u for u in range(8, 15)])
+    mean_sweeps = np.mean([2.0 ** v for v in range(10, 15)])
+    mean_job_s = mean_L2 * mean_sweeps / (saturated_flips_per_ns * 1e9)
+    rate = 0.8 / mean_job_s  # arrivals that keep the device 80 % busy
+    jobs = [Job(**d) for d in workloads.serving_jobs(args.jobs, rate)]
+    srv = Server(epoch=64)
+    stats = srv.run(jobs)
+    log(f"serving: {stats['jobs']} jobs in {stats['wall_s']:.2f} s, p50 {stats['latency_p50_s']:.3f} s, "
+        f"p99 {stats['latency_p99_s']:.3f} s")
+    stats.update({"arrival_rate_per_s": round(rate, 3), "offered_load": 0.8,
+                  "workload": "Poisson arrivals, L = 2^U (U uniform 8..14), sweeps 2^V (V uniform 10..14), "
+                              "Ising or Blume-Capel at T_c, admitted by slots and 80% of free HBM"})
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in stats.items()}
+
+
 def run(args):
     import torch
     import paper_2503_14688_amd as spin
@@ -84,7 +169,6 @@ def run(args):
 
     t_start = lat.t
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
-    meas_ev = []
     n_meas = 0
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
@@ -125,6 +209,13 @@ def run(args):
                      "algorithmic_bytes_per_launch": bytes_launch},
     }
     log(f"timed region done: {value:.1f} flips/ns")
+    del lat
+    torch.cuda.empty_cache()
+    if not args.skip_batched:
+        out["batched"] = run_batched(args)
+    if not args.skip_serving:
+        sat = out["batched"]["flips_per_ns"] if "batched" in out else out["sweep_only_flips_per_ns"]
+        out["serving"] = run_serving(args, sat)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
     return out
@@ -138,6 +229,12 @@ def main():
     ap.add_argument("--workload", default="ising_large", choices=["ising_large", "bc_large", "ising_check"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-serving", action="store_true")
+    ap.add_argument("--replicas", type=int, default=512)
+    ap.add_argument("--batch-sweeps", type=int, default=4096)
+    ap.add_argument("--compare-sweeps", type=int, default=256)
+    ap.add_argument("--jobs", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab decomposition "

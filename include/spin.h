@@ -187,6 +187,9 @@ typedef struct spin_replica_desc {
     void *dev_buf;      /* caller-owned, spin_lattice_bytes(model, L) bytes    */
     size_t buf_bytes;
     uint32_t schedule;  /* row of the schedule table this replica follows      */
+    uint64_t t0;        /* sweeps the replica has already done: its random
+                           stream continues at sweep index t0 (0 for a fresh
+                           lattice); schedule step k runs sweep t0 + k         */
 } spin_replica_desc;
 
 /* spin_batch_run flags */
@@ -194,21 +197,22 @@ typedef struct spin_replica_desc {
 #define SPIN_BATCH_ROWS4 2u   /* force 4 rows per thread                      */
 #define SPIN_BATCH_ROWS8 4u   /* force 8 rows per thread                      */
 
-/* Create a batch of n replicas (all at t = 0).  T holds n_sched schedules of
+/* Create a batch of n replicas.  T holds n_sched schedules of
  * n_steps temperatures each: T[s * n_steps + k] is the bath temperature of
  * sweep k for schedule s (host array, copied into threshold tables).  The
  * batch owns one handle per replica (spin_batch_replica) and works on
  * hip_stream, or on a stream of its own when hip_stream is NULL (a graph
  * cannot be captured on the legacy default stream).  -EINVAL as for
  * spin_create (message names the replica), or a schedule index out of range,
- * or a negative / NaN temperature. */
+ * or a negative / NaN temperature, or t0 + n_steps beyond 2^32. */
 int spin_batch_create(uint32_t n, const spin_replica_desc *reps, uint32_t n_sched, uint32_t n_steps,
                       const double *T, void *hip_stream, spin_batch **out);
 
 /* T = infinity start of every replica.  Asynchronous. */
 int spin_batch_init_random(spin_batch *b);
 
-/* Advance every replica by n sweeps (schedule steps t .. t + n - 1).  The
+/* Advance every replica by n sweeps (schedule steps t .. t + n - 1, replica
+ * sweep indices t0 + t .. t0 + t + n - 1, t = sweeps this batch has run).  The
  * first run chooses the tile shape (4 or 8 rows per thread) by timing both
  * on scratch copies of the lattices, unless a ROWS flag forces one.
  * Asynchronous; -EINVAL past the end of the schedule. */
@@ -220,7 +224,7 @@ int spin_batch_sync(spin_batch *b);
 /* Borrow replica k's handle (measure, get/set spins); owned by the batch. */
 int spin_batch_replica(spin_batch *b, uint32_t k, spin_handle **out);
 
-/* Replica count, sweeps done, tile shape in use (0 before the first run) and
+/* Replica count, sweeps this batch has run, tile shape in use (0 before the first run) and
  * tiles per half-sweep; any output may be NULL. */
 int spin_batch_info(const spin_batch *b, uint32_t *n_replicas, uint64_t *t, int *rows, uint64_t *tiles);
 

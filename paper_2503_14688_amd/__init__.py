@@ -44,7 +44,7 @@ BATCH_ROWS8 = 4
 class spin_replica_desc(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int), ("L", ctypes.c_uint32), ("seed", ctypes.c_uint64),
                 ("J", ctypes.c_double), ("Delta", ctypes.c_double), ("dev_buf", ctypes.c_void_p),
-                ("buf_bytes", ctypes.c_size_t), ("schedule", ctypes.c_uint32)]
+                ("buf_bytes", ctypes.c_size_t), ("schedule", ctypes.c_uint32), ("t0", ctypes.c_uint64)]
 
 
 EXPORTS = ["spin_lattice_bytes", "spin_create", "spin_init_random", "spin_sweep", "spin_sweep_ex",
@@ -327,7 +327,7 @@ class Batch:
             buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
             self.bufs.append(buf)
             descs.append(spin_replica_desc(r["model"], r["L"], r["seed"], r.get("J", 1.0), r.get("Delta", 0.0),
-                                           buf.data_ptr(), nbytes, r["schedule"]))
+                                           buf.data_ptr(), nbytes, r["schedule"], r.get("t0", 0)))
         self.b = spin_batch_create(descs, T)
 
     def init_random(self):

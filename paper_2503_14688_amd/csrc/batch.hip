@@ -20,6 +20,7 @@ using namespace spin_host;
 struct spin_batch {
     std::vector<spin_handle *> reps;
     std::vector<uint32_t> table_of;     // replica -> threshold table id
+    std::vector<uint64_t> t0;           // replica -> sweep index of schedule step 0
     uint32_t n_tables = 0, n_steps = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -81,6 +82,7 @@ int build_tiles(spin_batch *b, int rows)
     for (uint32_t r : order) {
         host[r].lat = b->reps[r]->lat;
         host[r].sched = b->table_of[r];
+        host[r].t0 = (uint32_t)b->t0[r];
         host[r].tile0 = next;
         for (uint64_t q = 0; q < tiles[r]; ++q)
             tile_rep.push_back(r);
@@ -104,7 +106,7 @@ int launch_sweeps(spin_batch *b, int rows, uint64_t t0, uint32_t n, hipStream_t 
         const uint64_t step = t0 + q;
         for (uint32_t c = 0; c < 2; ++c)
             HIP_TRY(spin::launch_batch_half_sweep(rows, b->d_reps[k], b->d_tile_rep[k], b->ntiles[k], b->d_tables,
-                                                  b->n_steps, (uint32_t)step, (uint32_t)step, c, st),
+                                                  b->n_steps, (uint32_t)step, c, st),
                     "batched sweep launch");
     }
     return 0;
@@ -123,10 +125,8 @@ int autotune(spin_batch *b)
         b->rows = 8;  // no room to tune: keep the default shape
         return 0;
     }
-    std::vector<spin::Lattice> saved;
     size_t off = 0;
     for (spin_handle *h : b->reps) {
-        saved.push_back(h->lat);
         HIP_TRY(hipMemcpyAsync(scratch + off, h->buf, h->buf_bytes, hipMemcpyDeviceToDevice, b->stream),
                 "hipMemcpyAsync");
         off += (h->buf_bytes + 255) / 256 * 256;
@@ -154,10 +154,13 @@ int autotune(spin_batch *b)
                 "hipMemcpy");
         spin::BatchReplica *keep = b->d_reps[k];
         b->d_reps[k] = d_tmp;
+        // the current schedule step is the only one known to exist: time it
         int rc = launch_sweeps(b, rows, b->t, 1, b->stream);  // warm-up
         if (!rc) {
             HIP_TRY(hipEventRecord(e0, b->stream), "hipEventRecord");
-            rc = launch_sweeps(b, rows, b->t, 2, b->stream);
+            rc = launch_sweeps(b, rows, b->t, 1, b->stream);
+            if (!rc)
+                rc = launch_sweeps(b, rows, b->t, 1, b->stream);
             HIP_TRY(hipEventRecord(e1, b->stream), "hipEventRecord");
             HIP_TRY(hipEventSynchronize(e1), "hipEventSynchronize");
         }
@@ -219,6 +222,10 @@ int spin_batch_create(uint32_t n, const spin_replica_desc *descs, uint32_t n_sch
             release(b);
             return fail(-EINVAL, "replica %u: schedule %u out of range", r, d.schedule);
         }
+        if (d.t0 + (uint64_t)n_steps > (1ull << 32)) {
+            release(b);
+            return fail(-EINVAL, "replica %u: sweep index t0 + steps passes 2^32", r);
+        }
         spin_handle *h = nullptr;
         int rc = spin_create(d.model, d.L, d.seed, d.J, d.Delta, d.dev_buf, d.buf_bytes, b->stream, &h);
         if (rc) {
@@ -226,7 +233,9 @@ int spin_batch_create(uint32_t n, const spin_replica_desc *descs, uint32_t n_sch
             release(b);
             return fail(rc, "replica %u: %s", r, msg.c_str());
         }
+        h->t = d.t0;
         b->reps.push_back(h);
+        b->t0.push_back(d.t0);
         auto key = std::make_tuple(d.model, d.J, d.Delta, d.schedule);
         auto it = ids.find(key);
         if (it == ids.end())
@@ -323,9 +332,9 @@ int spin_batch_run(spin_batch *b, uint32_t n, uint32_t flags)
         HIP_TRY(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
     }
     b->t += n;
-    for (spin_handle *h : b->reps) {
-        h->t = b->t;
-        h->em_valid = false;
+    for (size_t r = 0; r < b->reps.size(); ++r) {
+        b->reps[r]->t = b->t0[r] + b->t;
+        b->reps[r]->em_valid = false;
     }
     return 0;
 }

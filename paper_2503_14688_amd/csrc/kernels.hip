@@ -396,12 +396,12 @@ __global__ __launch_bounds__(kBlock) void k_sweep_bc(Lattice lat, uint32_t c, ui
 
 // Batched half-sweep: one launch advances colour c of every replica.  The
 // flat tile list maps each global tile to (replica, local tile); replica r's
-// thresholds for this sweep are tables[sched(r) * stride + step].
+// thresholds for this sweep are tables[sched(r) * stride + step] and its
+// random stream runs at sweep index t0(r) + step.
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica *reps, const uint32_t *tile_rep,
                                                              uint64_t ntiles, const GroupTable *tables,
-                                                             uint32_t stride, uint32_t step, uint32_t t,
-                                                             uint32_t c)
+                                                             uint32_t stride, uint32_t step, uint32_t c)
 {
     __shared__ IsingQueue<R> Q;
     unsigned long long e[kEmCounters] = {0, 0, 0, 0};
@@ -410,6 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica 
         const BatchReplica &rep = reps[rid];
         const GroupTable &gt = tables[(size_t)rep.sched * stride + step];
         const uint64_t local = tile - rep.tile0;
+        const uint32_t t = rep.t0 + step;
         if (rep.lat.model == kIsing)
             ising_tile<false, R>(rep.lat, c, t, gt, local, Q, e);
         else
@@ -631,17 +632,17 @@ uint64_t sweep_tiles(const Lattice &lat, int rows)
 }
 
 hipError_t launch_batch_half_sweep(int rows, const BatchReplica *reps, const uint32_t *tile_rep, uint64_t ntiles,
-                                   const GroupTable *tables, uint32_t stride, uint32_t step, uint32_t t,
-                                   uint32_t colour, hipStream_t st)
+                                   const GroupTable *tables, uint32_t stride, uint32_t step, uint32_t colour,
+                                   hipStream_t st)
 {
     if (rows == 4) {
         static const unsigned g = resident_grid(k_batch_half_sweep<4>, 0, ~0ull);
         hipLaunchKernelGGL(k_batch_half_sweep<4>, dim3(g < ntiles ? g : (unsigned)ntiles), dim3(kBlock), 0, st,
-                           reps, tile_rep, ntiles, tables, stride, step, t, colour);
+                           reps, tile_rep, ntiles, tables, stride, step, colour);
     } else if (rows == 8) {
         static const unsigned g = resident_grid(k_batch_half_sweep<8>, 0, ~0ull);
         hipLaunchKernelGGL(k_batch_half_sweep<8>, dim3(g < ntiles ? g : (unsigned)ntiles), dim3(kBlock), 0, st,
-                           reps, tile_rep, ntiles, tables, stride, step, t, colour);
+                           reps, tile_rep, ntiles, tables, stride, step, colour);
     } else {
         return hipErrorInvalidValue;
     }

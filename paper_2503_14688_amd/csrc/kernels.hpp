@@ -44,6 +44,7 @@ constexpr int kEmCounters = 4;
 struct BatchReplica {
     Lattice lat;
     uint32_t sched;
+    uint32_t t0;    // sweep index of schedule step 0
     uint64_t tile0;
 };
 
@@ -54,8 +55,8 @@ hipError_t launch_init(const Lattice &lat, hipStream_t st);
 constexpr int kBatchRowChoices[2] = {4, 8};
 uint64_t sweep_tiles(const Lattice &lat, int rows);
 hipError_t launch_batch_half_sweep(int rows, const BatchReplica *reps, const uint32_t *tile_rep, uint64_t ntiles,
-                                   const GroupTable *tables, uint32_t stride, uint32_t step, uint32_t t,
-                                   uint32_t colour, hipStream_t st);
+                                   const GroupTable *tables, uint32_t stride, uint32_t step, uint32_t colour,
+                                   hipStream_t st);
 hipError_t launch_half_sweep(const Lattice &lat, uint32_t colour, uint32_t t, const GroupTable &gt,
                              unsigned long long *em_acc, hipStream_t st);
 hipError_t launch_measure_em(const Lattice &lat, unsigned long long *em_acc, hipStream_t st);

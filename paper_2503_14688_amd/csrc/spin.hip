@@ -221,12 +221,7 @@ int spin_create(int model, uint32_t L, uint64_t seed, double J, double Delta, vo
     h->lat.model = model;
     h->lat.key0 = (uint32_t)seed;
     h->lat.key1 = (uint32_t)(seed >> 32);
-    int rc = ensure_acc(h, 64);
-    if (rc) {
-        delete h;
-        return rc;
-    }
-    *out = h;
+    *out = h;  // reduction scratch is allocated at the first measurement
     return 0;
 }
 
@@ -254,6 +249,9 @@ int spin_sweep_ex(spin_handle *h, uint32_t n, const double *T, uint32_t flags)
             return fail(-EINVAL, "T[%u] = %g is negative or NaN", k, T[k]);
     }
     const bool fuse = (flags & SPIN_FUSE_MEASURE) != 0;
+    if (fuse)
+        if (int rc = ensure_acc(h, 64))
+            return rc;
     if (fuse)
         HIP_TRY(spin::launch_fill_u64(h->d_acc, spin::kEmCounters, 0ull, h->stream), "fill kernel launch");
     if (n == 0) {

@@ -1,0 +1,172 @@
+"""Continuous-batching service for quench jobs (protocol 1 runs on demand).
+
+A job asks for a T = infinity start of one lattice (model, L, seed, J, Delta)
+followed by a number of sweeps at bath temperature T, and returns the final
+measurement (energy, magnetisation, C(r) on the sparse separation set, xi).
+
+Scheduling: jobs wait in a FIFO queue.  At every epoch boundary the server
+admits queued jobs while a slot is free and the device-memory budget holds
+the new lattice; admitted lattices stay resident in HBM until their job ends.
+One epoch advances every active job by the same number of sweeps through one
+spin_batch (one launch per half-sweep covers all active lattices, captured as
+a HIP graph), so work of jobs that arrived at different times overlaps on the
+device.  A finished job is measured, its lattice freed, and its slot reused
+at the next boundary.  Each replica of an epoch continues its own random
+stream (descriptor t0 = sweeps already done), so a job's result does not
+depend on which other jobs shared its epochs.
+
+The device work sits behind a small backend interface (GpuBackend here); the
+scheduler itself is plain host logic.
+"""
+import time
+from collections import deque
+
+import numpy as np
+
+from . import (BATCH_ROWS8, spin_batch_create, spin_batch_destroy, spin_batch_run, spin_create,
+               spin_destroy, spin_get_spins, spin_init_random, spin_lattice_bytes, spin_measure,
+               spin_replica_desc, spin_set_t)
+from . import workloads
+
+
+class Job:
+    def __init__(self, id, model, L, sweeps, seed, T, J=1.0, Delta=0.0, arrival=0.0, **_):
+        self.id, self.model, self.L, self.sweeps = id, model, L, sweeps
+        self.seed, self.T, self.J, self.Delta = seed, T, J, Delta
+        self.arrival = arrival
+        self.bytes = spin_lattice_bytes(model, L)
+        self.done = 0
+        self.state = None  # backend-owned lattice state
+        self.admitted_at = None
+        self.finished_at = None
+        self.result = None
+        self.spins = None
+
+
+class GpuBackend:
+    """Lattices in torch device buffers; one spin_batch per epoch."""
+
+    def __init__(self, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(self.device)
+
+    def free_bytes(self):
+        free, _ = self.torch.cuda.mem_get_info(self.device)
+        return free
+
+    def admit(self, job):
+        with self.torch.cuda.stream(self.stream):
+            buf = self.torch.empty(job.bytes, dtype=self.torch.uint8, device=self.device)
+        h = spin_create(job.model, job.L, job.seed, job.J, job.Delta, buf.data_ptr(), job.bytes,
+                        self.stream.cuda_stream)
+        spin_init_random(h)
+        job.state = (buf, h)
+
+    def epoch(self, jobs, n):
+        temps = sorted({j.T for j in jobs})
+        T = np.array([[tk] * n for tk in temps], dtype=np.float64)
+        descs = [spin_replica_desc(j.model, j.L, j.seed, j.J, j.Delta, j.state[0].data_ptr(), j.bytes,
+                                   temps.index(j.T), j.done) for j in jobs]
+        b = spin_batch_create(descs, T, self.stream.cuda_stream)
+        try:
+            spin_batch_run(b, n, BATCH_ROWS8)
+        finally:
+            spin_batch_destroy(b)  # waits for the epoch's work
+
+    def finish(self, job, r, keep_spins):
+        buf, h = job.state
+        spin_set_t(h, job.done)
+        job.result = spin_measure(h, r)
+        if keep_spins:
+            job.spins = spin_get_spins(h, job.L)
+        spin_destroy(h)
+        job.state = None
+
+
+class Server:
+    """Admission by slots and memory budget, epochs of continuous batching."""
+
+    def __init__(self, max_slots=256, mem_budget=None, epoch=64, keep_spins=False, backend=None):
+        self.backend = backend if backend is not None else GpuBackend()
+        if mem_budget is None:
+            mem_budget = int(0.8 * self.backend.free_bytes())
+        self.max_slots = max_slots
+        self.mem_budget = mem_budget
+        self.epoch = epoch
+        self.keep_spins = keep_spins
+        self.queue = deque()
+        self.active = []
+        self.finished = []
+        self.bytes_in_use = 0
+        self.peak_bytes = 0
+        self.peak_active = 0
+        self.epochs = 0
+        self.flips = 0
+
+    def submit(self, job):
+        self.queue.append(job)
+
+    def _admit(self, now):
+        while self.queue and len(self.active) < self.max_slots:
+            job = self.queue[0]
+            if self.bytes_in_use + job.bytes > self.mem_budget:
+                if not self.active and job.bytes > self.mem_budget:
+                    raise MemoryError(f"job {job.id} needs {job.bytes} bytes, budget is {self.mem_budget}")
+                break  # FIFO: wait until memory frees up
+            self.queue.popleft()
+            self.backend.admit(job)
+            job.admitted_at = now
+            self.bytes_in_use += job.bytes
+            self.active.append(job)
+        self.peak_bytes = max(self.peak_bytes, self.bytes_in_use)
+        self.peak_active = max(self.peak_active, len(self.active))
+
+    def _run_epoch(self):
+        n = min(self.epoch, min(j.sweeps - j.done for j in self.active))
+        self.backend.epoch(self.active, n)
+        for j in self.active:
+            j.done += n
+            self.flips += n * j.L * j.L
+        self.epochs += 1
+
+    def _retire(self, now, r_of):
+        still = []
+        for j in self.active:
+            if j.done < j.sweeps:
+                still.append(j)
+                continue
+            self.backend.finish(j, r_of(j.L), self.keep_spins)
+            self.bytes_in_use -= j.bytes
+            j.finished_at = now()
+            self.finished.append(j)
+        self.active = still
+
+    def run(self, jobs, realtime=True, r_of=workloads.r_sparse):
+        """Serve jobs (arrival times in seconds from start); returns stats.
+        With realtime=False every job is queued at once in arrival order."""
+        pending = sorted(jobs, key=lambda j: j.arrival)
+        t0 = time.perf_counter()
+
+        def now():
+            return time.perf_counter() - t0
+
+        k = 0
+        while k < len(pending) or self.queue or self.active:
+            tnow = now()
+            while k < len(pending) and (pending[k].arrival <= tnow or not realtime):
+                self.submit(pending[k])
+                k += 1
+            self._admit(tnow)
+            if self.active:
+                self._run_epoch()
+                self._retire(now, r_of)
+            elif k < len(pending):
+                time.sleep(max(0.0, pending[k].arrival - now()))
+        wall = now()
+        lat = np.array([j.finished_at - j.arrival for j in self.finished])
+        return {"jobs": len(self.finished), "wall_s": wall, "jobs_per_s": len(self.finished) / wall,
+                "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+                "epochs": self.epochs, "flips_per_ns": self.flips / wall / 1e9,
+                "peak_active": self.peak_active, "peak_bytes": self.peak_bytes}
