@@ -244,16 +244,20 @@ int spin_batch_create(uint32_t n, const spin_replica_desc *descs, uint32_t n_sch
     }
     b->n_tables = (uint32_t)ids.size();
     std::vector<GroupTable> tables((size_t)b->n_tables * n_steps);
+    std::vector<uint32_t> layout(ids.size());  // bc_groups of each table's replicas
+    for (uint32_t r = 0; r < n; ++r)
+        layout[b->table_of[r]] = b->reps[r]->lat.bc_groups;
     for (const auto &kv : ids) {
         const int model = std::get<0>(kv.first);
         const double J = std::get<1>(kv.first), Delta = std::get<2>(kv.first);
         const uint32_t s = std::get<3>(kv.first);
+        const uint32_t bc_groups = layout[kv.second];
         for (uint32_t k = 0; k < n_steps; ++k) {
             const double Tk = T[(size_t)s * n_steps + k];
             if (k > 0 && Tk == T[(size_t)s * n_steps + k - 1])
                 tables[(size_t)kv.second * n_steps + k] = tables[(size_t)kv.second * n_steps + k - 1];
             else
-                tables[(size_t)kv.second * n_steps + k] = make_groups(model, J, Delta, Tk);
+                tables[(size_t)kv.second * n_steps + k] = make_groups(model, bc_groups, J, Delta, Tk);
         }
     }
     hipError_t e = hipMalloc(&b->d_tables, tables.size() * sizeof(GroupTable));

@@ -34,8 +34,9 @@ namespace spin_host {
 // Record a failure for spin_last_error() and return code.
 int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
-// Acceptance-group table of a model at bath temperature T (host FP64 exp).
-GroupTable make_groups(int model, double J, double Delta, double T);
+// Acceptance-group table of a model at bath temperature T (host FP64 exp),
+// for the lattice's Blume-Capel group layout bc_groups.
+GroupTable make_groups(int model, uint32_t bc_groups, double J, double Delta, double T);
 int ensure_acc(spin_handle *h, size_t entries);
 
 } // namespace spin_host

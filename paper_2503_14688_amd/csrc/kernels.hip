@@ -270,7 +270,7 @@ __device__ __forceinline__ Pair load_pair(const uint32_t *plane, size_t word)
 // Blume-Capel half-sweep of one tile: per word the proposal plane, the
 // bit-sliced y = s_eff * h (neighbour sum seen from the sign that the move
 // carries), the 13 acceptance groups and the lazy Metropolis test.
-template <bool MEASURE, int R>
+template <bool MEASURE, int R, int NG>
 __device__ __forceinline__ void bc_tile(const Lattice &lat, uint32_t c, uint32_t t, const GroupTable &gt,
                                         uint64_t tile, unsigned long long (&e)[kEmCounters])
 {
@@ -281,9 +281,9 @@ __device__ __forceinline__ void bc_tile(const Lattice &lat, uint32_t c, uint32_t
     const uint64_t g = tile * kBlock + threadIdx.x;
     if (g >= nitems)
         return;
-    uint32_t thr[kBcGroups];
+    uint32_t thr[NG];
 #pragma unroll
-    for (int q = 0; q < kBcGroups; ++q)
+    for (int q = 0; q < NG; ++q)
         thr[q] = gt.thr[q];
     const uint32_t rg = (uint32_t)(g / W);
     const uint32_t w = (uint32_t)(g - (uint64_t)rg * W);
@@ -328,18 +328,32 @@ __device__ __forceinline__ void bc_tile(const Lattice &lat, uint32_t c, uint32_t
         const uint32_t famA = s.z & ~X;  // s -> 0:   dE = J y - Delta
         const uint32_t famB = ~s.z;      // 0 -> s':  dE = -J y + Delta
         const uint32_t famC = s.z & X;   // s -> -s:  dE = 2 J y
-        uint32_t need[kBcGroups];
+        uint32_t mask[NG];
+        if constexpr (NG == kBcGroups) {
+            // general Delta: for each y one of {s -> 0, 0 -> s'} can have dE > 0
+            // (sel_a picks it); s -> -s has dE > 0 for y > 0
+#pragma unroll
+            for (int q = 0; q < NG; ++q)
+                mask[q] = q < 9 ? ((((gt.sel_a_bits >> q) & 1u) ? famA : famB) & Y[q]) : (famC & Y[q - 4]);
+        } else {
+            // Delta = 0: dE = J y (s -> 0), -J y (0 -> s'), 2 J y (s -> -s); v = y + 4
+            mask[0] = (famA & Y[5]) | (famB & Y[3]);                 // dE = J
+            mask[1] = (famA & Y[6]) | (famB & Y[2]) | (famC & Y[5]);  // 2J
+            mask[2] = (famA & Y[7]) | (famB & Y[1]);                 // 3J
+            mask[3] = (famA & Y[8]) | (famB & Y[0]) | (famC & Y[6]);  // 4J
+            mask[4] = famC & Y[7];                                   // 6J
+            mask[5] = famC & Y[8];                                   // 8J
+        }
+        uint32_t need[NG];
         uint32_t never = 0, any = 0;
 #pragma unroll
-        for (int q = 0; q < kBcGroups; ++q) {
-            const uint32_t mask = q < 9 ? ((((gt.sel_a_bits >> q) & 1u) ? famA : famB) & Y[q])
-                                        : (famC & Y[q - 4]);
-            need[q] = ((gt.rng_bits >> q) & 1u) ? mask : 0u;
-            never |= ((gt.never_bits >> q) & 1u) ? mask : 0u;
+        for (int q = 0; q < NG; ++q) {
+            need[q] = ((gt.rng_bits >> q) & 1u) ? mask[q] : 0u;
+            never |= ((gt.never_bits >> q) & 1u) ? mask[q] : 0u;
             any |= need[q];
         }
         const uint32_t always = ~(any | never);
-        const uint32_t F = metropolis_accept<kBcGroups>(need, thr, always, i, w, t, c, lat.key0, lat.key1);
+        const uint32_t F = metropolis_accept<NG>(need, thr, always, i, w, t, c, lat.key0, lat.key1);
         const uint32_t zp = ~s.z | X;          // proposed s' != 0
         const uint32_t sp = X & ~(s.z & s.s);  // proposed s' < 0
         const uint32_t nz = (F & zp) | (~F & s.z);
@@ -388,8 +402,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep_bc(Lattice lat, uint32_t c, ui
 {
     unsigned long long e[kEmCounters] = {0, 0, 0, 0};
     const uint64_t ntiles = tiles_of<kRows>(lat);
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-        bc_tile<MEASURE, kRows>(lat, c, t, gt, tile, e);
+    if (lat.bc_groups == kBcGroupsDelta0) {
+        for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+            bc_tile<MEASURE, kRows, kBcGroupsDelta0>(lat, c, t, gt, tile, e);
+    } else {
+        for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+            bc_tile<MEASURE, kRows, kBcGroups>(lat, c, t, gt, tile, e);
+    }
     if (MEASURE)
         block_reduce_atomic<kEmCounters>(e, acc);
 }
@@ -413,8 +432,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica 
         const uint32_t t = rep.t0 + step;
         if (rep.lat.model == kIsing)
             ising_tile<false, R>(rep.lat, c, t, gt, local, Q, e);
+        else if (rep.lat.bc_groups == kBcGroupsDelta0)
+            bc_tile<false, R, kBcGroupsDelta0>(rep.lat, c, t, gt, local, e);
         else
-            bc_tile<false, R>(rep.lat, c, t, gt, local, e);
+            bc_tile<false, R, kBcGroups>(rep.lat, c, t, gt, local, e);
     }
 }
 

@@ -14,6 +14,9 @@ enum Model : int { kIsing = 0, kBlumeCapel = 1 };
 // families can have dE > 0 for a given y) and four for s -> -s at y = 1..4.
 constexpr int kIsingGroups = 2;
 constexpr int kBcGroups = 13;
+// Blume-Capel with Delta = 0: the positive energy changes are J {1,2,3,4,6,8},
+// so the 13 groups merge into 6 (see bc_tile).
+constexpr int kBcGroupsDelta0 = 6;
 constexpr int kMaxGroups = 16;
 
 struct GroupTable {
@@ -31,6 +34,7 @@ struct Lattice {
     uint64_t plane_u32;// uint32 words per colour plane (L * W, doubled for BC)
     int model;
     uint32_t key0, key1;
+    uint32_t bc_groups;  // Blume-Capel acceptance groups in use: 13, or 6 when Delta = 0
 };
 
 // Counters of the energy/magnetisation reduction (both colours):

@@ -75,12 +75,52 @@ void set_group(GroupTable &gt, int g, Rule rule, uint32_t thr)
         gt.never_bits |= 1u << g;
 }
 
-// Group tables as the kernels consume them (see kernels.hpp).
-GroupTable make_groups(int model, double J, double Delta, double T)
+// Blume-Capel groups merged for Delta = 0 (kernels.hip, bc_tile): members
+// (s, s', h) per group; every member must give the same threshold.
+struct Member {
+    int s, sp, h;
+};
+const Member kMerged[6][3] = {
+    {{1, 0, 1}, {0, 1, -1}, {0, 1, -1}},   // dE = J
+    {{1, 0, 2}, {0, 1, -2}, {1, -1, 1}},   // 2J
+    {{1, 0, 3}, {0, 1, -3}, {0, 1, -3}},   // 3J
+    {{1, 0, 4}, {0, 1, -4}, {1, -1, 2}},   // 4J
+    {{1, -1, 3}, {1, -1, 3}, {1, -1, 3}},  // 6J
+    {{1, -1, 4}, {1, -1, 4}, {1, -1, 4}},  // 8J
+};
+
+bool merged_groups(double J, double Delta, double T, GroupTable &gt)
+{
+    if (Delta != 0.0)
+        return false;
+    std::memset(&gt, 0, sizeof gt);
+    for (int g = 0; g < 6; ++g) {
+        uint32_t thr0 = 0;
+        const Rule r0 = metropolis_rule(delta_energy(J, Delta, kMerged[g][0].s, kMerged[g][0].sp, kMerged[g][0].h),
+                                        T, &thr0);
+        for (int k = 1; k < 3; ++k) {
+            uint32_t thr;
+            const Rule r = metropolis_rule(
+                delta_energy(J, Delta, kMerged[g][k].s, kMerged[g][k].sp, kMerged[g][k].h), T, &thr);
+            if (r != r0 || thr != thr0)
+                return false;
+        }
+        set_group(gt, g, r0, thr0);
+    }
+    return true;
+}
+
+// Group tables as the kernels consume them (see kernels.hpp): bc_groups is
+// the lattice's Blume-Capel group layout (13 general, 6 for Delta = 0).
+GroupTable make_groups(int model, uint32_t bc_groups, double J, double Delta, double T)
 {
     GroupTable gt;
     std::memset(&gt, 0, sizeof gt);
     uint32_t thr;
+    if (model == SPIN_BLUME_CAPEL && bc_groups == spin::kBcGroupsDelta0) {
+        merged_groups(J, Delta, T, gt);  // exactness checked when the layout was chosen
+        return gt;
+    }
     if (model == SPIN_ISING) {
         // three aligned neighbours (s h = 2) and four (s h = 4)
         Rule r = metropolis_rule(delta_energy(J, Delta, 1, -1, 2), T, &thr);
@@ -221,6 +261,14 @@ int spin_create(int model, uint32_t L, uint64_t seed, double J, double Delta, vo
     h->lat.model = model;
     h->lat.key0 = (uint32_t)seed;
     h->lat.key1 = (uint32_t)(seed >> 32);
+    h->lat.bc_groups = spin::kBcGroups;
+    {
+        // merged groups need every member to give the same dE; that does not
+        // depend on T, so one check decides for all temperatures
+        GroupTable probe;
+        if (model == SPIN_BLUME_CAPEL && merged_groups(J, Delta, 1.0, probe))
+            h->lat.bc_groups = spin::kBcGroupsDelta0;
+    }
     *out = h;  // reduction scratch is allocated at the first measurement
     return 0;
 }
@@ -266,7 +314,7 @@ int spin_sweep_ex(spin_handle *h, uint32_t n, const double *T, uint32_t flags)
     double last_T = std::nan("");
     for (uint32_t k = 0; k < n; ++k) {
         if (!(T[k] == last_T)) {
-            gt = make_groups(h->model, h->J, h->Delta, T[k]);
+            gt = make_groups(h->model, h->lat.bc_groups, h->J, h->Delta, T[k]);
             last_T = T[k];
         }
         const uint32_t t = (uint32_t)(h->t + k);
