@@ -88,7 +88,7 @@ def run_batched(args):
     b.sync()
     full_s = time.perf_counter() - t0
     info = b.info()
-    log(f"batched: {args.replicas} replicas x {n_steps} sweeps in {full_s:.3f} s (rows per thread {info['rows']})")
+    log(f"batched: {args.replicas} replicas x {n_steps} sweeps in {full_s:.3f} s (strategy {info['variant']})")
     b.close()
 
     cmp_sweeps = min(args.compare_sweeps, n_steps)
@@ -99,7 +99,7 @@ def run_batched(args):
     b = spin.Batch(reps, T).init_random()
     b.sync()
     t0 = time.perf_counter()
-    b.run(cmp_sweeps, spin.BATCH_ROWS8 if info["rows"] == 8 else spin.BATCH_ROWS4)
+    b.run(cmp_sweeps, spin.BATCH_VARIANT(info["variant"]))
     b.sync()
     batched_s = time.perf_counter() - t0
     plain = [spin.Lattice(r["model"], r["L"], r["seed"], r["J"], r["Delta"]).init_random() for r in reps]
@@ -118,7 +118,7 @@ def run_batched(args):
     return {"workload": f"{n} replicas, L in {{256,512,1024,2048}}, half Ising half Blume-Capel, "
                         f"T(t) = Tf + (T0 - Tf) exp(-t/tau), tau in {{64,256,1024}}",
             "replica_sweeps_per_s": round(n * n_steps / full_s, 1), "sweeps": n_steps,
-            "flips_per_ns": round(flips_per_sweep * n_steps / full_s / 1e9, 2), "rows_per_thread": info["rows"],
+            "flips_per_ns": round(flips_per_sweep * n_steps / full_s / 1e9, 2), "strategy": info["variant"],
             "compare_sweeps": cmp_sweeps,
             "batched_replica_sweeps_per_s": round(n * cmp_sweeps / batched_s, 1),
             "plain_replica_sweeps_per_s": round(n * cmp_sweeps / plain_s, 1),
@@ -158,8 +158,10 @@ def run(args):
     torch.cuda.init()
     stream = torch.cuda.current_stream()
     lat = spin.Lattice(model, L, seed, J, Delta, stream=stream)
+    strategy = lat.tune(T) if args.variant < 0 else args.variant
+    lat.variant = strategy
     lat.init_random()
-    log(f"allocated and initialised {wl['name']} ({lat.buf.numel() / 2**30:.1f} GiB)")
+    log(f"allocated and initialised {wl['name']} ({lat.buf.numel() / 2**30:.1f} GiB), sweep strategy {strategy}")
     Tk = np.array([T])
     for _ in range(args.warmup):
         lat.sweep(Tk)
@@ -200,7 +202,7 @@ def run(args):
         "config": {"workload": wl["name"], "model": "ising" if model == 0 else "blume-capel", "L": L,
                    "spins": L * L, "T": T, "J": J, "Delta": Delta, "seed": seed,
                    "measure": f"E, M, C(r) on {len(r)} separations <= {int(r[-1])} at sweeps 2^k",
-                   "measurements_timed": n_meas},
+                   "measurements_timed": n_meas, "sweep_strategy": strategy},
         "sweep_only_flips_per_ns": round(flips / (sweep_ms / 1e3) / 1e9, 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
@@ -221,6 +223,20 @@ def run(args):
     return out
 
 
+def calibrate_copy(gib=8):
+    """A plain device copy of known size (for scaling HBM traffic counters)."""
+    import torch
+    n = gib << 30
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copied {gib} GiB three times")
+    print(json.dumps({"calibration": "device copy", "bytes_read_per_copy": n, "bytes_written_per_copy": n}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,7 +251,13 @@ def main():
     ap.add_argument("--batch-sweeps", type=int, default=4096)
     ap.add_argument("--compare-sweeps", type=int, default=256)
     ap.add_argument("--jobs", type=int, default=64)
+    ap.add_argument("--variant", type=int, default=-1, help="sweep strategy (default: tuned)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 8 GiB device copy (traffic-counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab decomposition "
               "is a design, not part of this build", file=sys.stderr)

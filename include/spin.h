@@ -158,6 +158,17 @@ int spin_get_t(const spin_handle *h, uint64_t *t);
 int spin_threshold_table(int model, double J, double Delta, double T, uint32_t *out,
                          uint8_t *always, int capacity);
 
+/* Sweep strategy of a handle (results never depend on it; speed does):
+ *   0: 8 rows per thread, each thread finishes its words' random planes
+ *   1: 4 rows per thread, undecided Ising words go through a block queue
+ *   2: 8 rows per thread, block queue      3: 4 rows per thread, per word
+ * spin_set_variant sets one (-EINVAL outside 0..3); spin_tune times every
+ * strategy on a scratch lattice of the handle's model and size (capped at
+ * L = 16384) at bath temperature T and keeps the fastest. */
+int spin_set_variant(spin_handle *h, int variant);
+int spin_get_variant(const spin_handle *h, int *variant);
+int spin_tune(spin_handle *h, double T, int *chosen);
+
 /* Fill out[k] = T(t0 + k), k < n, for a schedule kind (host FP64). */
 int spin_schedule_fill(int kind, const double *params, uint64_t t0, uint32_t n, double *out);
 
@@ -192,10 +203,11 @@ typedef struct spin_replica_desc {
                            lattice); schedule step k runs sweep t0 + k         */
 } spin_replica_desc;
 
-/* spin_batch_run flags */
-#define SPIN_BATCH_DIRECT 1u  /* launch directly instead of capturing a graph */
-#define SPIN_BATCH_ROWS4 2u   /* force 4 rows per thread                      */
-#define SPIN_BATCH_ROWS8 4u   /* force 8 rows per thread                      */
+/* spin_batch_run flags: SPIN_BATCH_DIRECT launches directly instead of
+ * capturing a graph; SPIN_BATCH_VARIANT(v) forces sweep strategy v (see
+ * spin_set_variant) instead of the tuned one. */
+#define SPIN_BATCH_DIRECT 1u
+#define SPIN_BATCH_VARIANT(v) ((uint32_t)((v) + 1) << 4)
 
 /* Create a batch of n replicas.  T holds n_sched schedules of
  * n_steps temperatures each: T[s * n_steps + k] is the bath temperature of
@@ -213,9 +225,9 @@ int spin_batch_init_random(spin_batch *b);
 
 /* Advance every replica by n sweeps (schedule steps t .. t + n - 1, replica
  * sweep indices t0 + t .. t0 + t + n - 1, t = sweeps this batch has run).  The
- * first run chooses the tile shape (4 or 8 rows per thread) by timing both
- * on scratch copies of the lattices, unless a ROWS flag forces one.
- * Asynchronous; -EINVAL past the end of the schedule. */
+ * first run chooses the sweep strategy by timing each on scratch copies of
+ * the lattices, unless SPIN_BATCH_VARIANT forces one.  Asynchronous; -EINVAL
+ * past the end of the schedule. */
 int spin_batch_run(spin_batch *b, uint32_t n, uint32_t flags);
 
 /* Wait for the batch's queued work. */
@@ -224,9 +236,9 @@ int spin_batch_sync(spin_batch *b);
 /* Borrow replica k's handle (measure, get/set spins); owned by the batch. */
 int spin_batch_replica(spin_batch *b, uint32_t k, spin_handle **out);
 
-/* Replica count, sweeps this batch has run, tile shape in use (0 before the first run) and
- * tiles per half-sweep; any output may be NULL. */
-int spin_batch_info(const spin_batch *b, uint32_t *n_replicas, uint64_t *t, int *rows, uint64_t *tiles);
+/* Replica count, sweeps this batch has run, sweep strategy in use (-1 before
+ * the first run) and tiles per half-sweep; any output may be NULL. */
+int spin_batch_info(const spin_batch *b, uint32_t *n_replicas, uint64_t *t, int *variant, uint64_t *tiles);
 
 /* Release the batch, its handles and device tables (never the lattices). */
 int spin_batch_destroy(spin_batch *b);

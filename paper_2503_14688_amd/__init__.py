@@ -37,8 +37,12 @@ class spin_meas(ctypes.Structure):
 
 
 BATCH_DIRECT = 1
-BATCH_ROWS4 = 2
-BATCH_ROWS8 = 4
+
+
+def BATCH_VARIANT(v):
+    """spin_batch_run flag forcing sweep strategy v."""
+    return (v + 1) << 4
+
 
 
 class spin_replica_desc(ctypes.Structure):
@@ -50,6 +54,7 @@ class spin_replica_desc(ctypes.Structure):
 EXPORTS = ["spin_lattice_bytes", "spin_create", "spin_init_random", "spin_sweep", "spin_sweep_ex",
            "spin_measure", "spin_get_spins", "spin_get_window", "spin_set_spins", "spin_set_t",
            "spin_get_t", "spin_threshold_table", "spin_schedule_fill", "spin_destroy",
+           "spin_set_variant", "spin_get_variant", "spin_tune",
            "spin_last_error", "spin_batch_create", "spin_batch_init_random", "spin_batch_run",
            "spin_batch_sync", "spin_batch_replica", "spin_batch_info", "spin_batch_destroy"]
 
@@ -89,6 +94,9 @@ def load_library():
         "spin_schedule_fill": (ctypes.c_int, [ctypes.c_int, f64p, ctypes.c_uint64, ctypes.c_uint32,
                                               f64p]),
         "spin_destroy": (ctypes.c_int, [vp]),
+        "spin_set_variant": (ctypes.c_int, [vp, ctypes.c_int]),
+        "spin_get_variant": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int)]),
+        "spin_tune": (ctypes.c_int, [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_int)]),
         "spin_last_error": (ctypes.c_char_p, []),
         "spin_batch_create": (ctypes.c_int, [ctypes.c_uint32, ctypes.POINTER(spin_replica_desc), ctypes.c_uint32,
                                              ctypes.c_uint32, f64p, vp, ctypes.POINTER(vp)]),
@@ -208,6 +216,22 @@ def spin_destroy(h):
     _check(load_library().spin_destroy(h))
 
 
+def spin_set_variant(h, v):
+    _check(load_library().spin_set_variant(h, v))
+
+
+def spin_get_variant(h):
+    v = ctypes.c_int()
+    _check(load_library().spin_get_variant(h, ctypes.byref(v)))
+    return v.value
+
+
+def spin_tune(h, T):
+    v = ctypes.c_int()
+    _check(load_library().spin_tune(h, T, ctypes.byref(v)))
+    return v.value
+
+
 def spin_last_error():
     return load_library().spin_last_error().decode()
 
@@ -243,11 +267,11 @@ def spin_batch_replica(b, k):
 def spin_batch_info(b):
     n = ctypes.c_uint32()
     t = ctypes.c_uint64()
-    rows = ctypes.c_int()
+    variant = ctypes.c_int()
     tiles = ctypes.c_uint64()
-    _check(load_library().spin_batch_info(b, ctypes.byref(n), ctypes.byref(t), ctypes.byref(rows),
+    _check(load_library().spin_batch_info(b, ctypes.byref(n), ctypes.byref(t), ctypes.byref(variant),
                                           ctypes.byref(tiles)))
-    return {"replicas": n.value, "t": t.value, "rows": rows.value, "tiles": tiles.value}
+    return {"replicas": n.value, "t": t.value, "variant": variant.value, "tiles": tiles.value}
 
 
 def spin_batch_destroy(b):
@@ -284,6 +308,17 @@ class Lattice:
 
     def spins(self):
         return spin_get_spins(self.h, self.L)
+
+    @property
+    def variant(self):
+        return spin_get_variant(self.h)
+
+    @variant.setter
+    def variant(self, v):
+        spin_set_variant(self.h, v)
+
+    def tune(self, T):
+        return spin_tune(self.h, T)
 
     def window(self, i0, j0, rows, cols):
         return spin_get_window(self.h, i0, j0, rows, cols)

@@ -25,7 +25,7 @@ struct spin_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     uint64_t t = 0;                      // sweeps done (schedule step)
-    int rows = 0;                        // tile shape in use (4 or 8; 0 = tune at first run)
+    int variant = -1;                    // sweep strategy in use (-1: tune at first run)
     spin::BatchReplica *d_reps[2] = {nullptr, nullptr};  // per tile shape
     uint32_t *d_tile_rep[2] = {nullptr, nullptr};
     uint64_t ntiles[2] = {0, 0};
@@ -37,6 +37,7 @@ struct spin_batch {
 namespace {
 
 int shape_index(int rows) { return rows == 4 ? 0 : 1; }
+int shape_of(int variant) { return shape_index(spin::variant_rows(variant)); }
 
 void release(spin_batch *b)
 {
@@ -99,21 +100,21 @@ int build_tiles(spin_batch *b, int rows)
     return 0;
 }
 
-int launch_sweeps(spin_batch *b, int rows, uint64_t t0, uint32_t n, hipStream_t st)
+int launch_sweeps(spin_batch *b, int variant, uint64_t t0, uint32_t n, hipStream_t st)
 {
-    const int k = shape_index(rows);
+    const int k = shape_of(variant);
     for (uint32_t q = 0; q < n; ++q) {
         const uint64_t step = t0 + q;
         for (uint32_t c = 0; c < 2; ++c)
-            HIP_TRY(spin::launch_batch_half_sweep(rows, b->d_reps[k], b->d_tile_rep[k], b->ntiles[k], b->d_tables,
-                                                  b->n_steps, (uint32_t)step, c, st),
+            HIP_TRY(spin::launch_batch_half_sweep(variant, b->d_reps[k], b->d_tile_rep[k], b->ntiles[k],
+                                                  b->d_tables, b->n_steps, (uint32_t)step, c, st),
                     "batched sweep launch");
     }
     return 0;
 }
 
-// Choose the tile shape: copy every lattice to scratch memory, time two
-// sweeps of each shape on the copies with HIP events, keep the faster.
+// Choose the sweep strategy: copy every lattice to scratch memory, time two
+// sweeps of each strategy on the copies with HIP events, keep the fastest.
 int autotune(spin_batch *b)
 {
     size_t total = 0;
@@ -122,7 +123,7 @@ int autotune(spin_batch *b)
     char *scratch = nullptr;
     if (hipMalloc(&scratch, total) != hipSuccess) {
         (void)hipGetLastError();
-        b->rows = 8;  // no room to tune: keep the default shape
+        b->variant = 0;  // no room to tune: keep the default strategy
         return 0;
     }
     size_t off = 0;
@@ -133,12 +134,12 @@ int autotune(spin_batch *b)
     }
     // descriptor copies pointing at the scratch lattices
     float best_ms = 0.0f;
-    int best = 8;
+    int best = 0;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
     HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
-    for (int rows : spin::kBatchRowChoices) {
-        const int k = shape_index(rows);
+    for (int v = 0; v < spin::kVariants; ++v) {
+        const int k = shape_of(v);
         std::vector<spin::BatchReplica> host(b->reps.size());
         HIP_TRY(hipMemcpy(host.data(), b->d_reps[k], host.size() * sizeof(spin::BatchReplica),
                           hipMemcpyDeviceToHost),
@@ -155,12 +156,12 @@ int autotune(spin_batch *b)
         spin::BatchReplica *keep = b->d_reps[k];
         b->d_reps[k] = d_tmp;
         // the current schedule step is the only one known to exist: time it
-        int rc = launch_sweeps(b, rows, b->t, 1, b->stream);  // warm-up
+        int rc = launch_sweeps(b, v, b->t, 1, b->stream);  // warm-up
         if (!rc) {
             HIP_TRY(hipEventRecord(e0, b->stream), "hipEventRecord");
-            rc = launch_sweeps(b, rows, b->t, 1, b->stream);
+            rc = launch_sweeps(b, v, b->t, 1, b->stream);
             if (!rc)
-                rc = launch_sweeps(b, rows, b->t, 1, b->stream);
+                rc = launch_sweeps(b, v, b->t, 1, b->stream);
             HIP_TRY(hipEventRecord(e1, b->stream), "hipEventRecord");
             HIP_TRY(hipEventSynchronize(e1), "hipEventSynchronize");
         }
@@ -172,14 +173,14 @@ int autotune(spin_batch *b)
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
         if (best_ms == 0.0f || ms < best_ms) {
             best_ms = ms;
-            best = rows;
+            best = v;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
     (void)hipFree(scratch);
-    b->rows = best;
+    b->variant = best;
     return 0;
 }
 
@@ -267,7 +268,7 @@ int spin_batch_create(uint32_t n, const spin_replica_desc *descs, uint32_t n_sch
         release(b);
         return hip_fail(e, "threshold tables");
     }
-    for (int rows : spin::kBatchRowChoices) {
+    for (int rows : {4, 8}) {
         int rc = build_tiles(b, rows);
         if (rc) {
             std::string msg = spin_last_error();
@@ -293,22 +294,21 @@ int spin_batch_run(spin_batch *b, uint32_t n, uint32_t flags)
 {
     if (!b)
         return fail(-EINVAL, "NULL batch");
-    if (flags & ~(SPIN_BATCH_DIRECT | SPIN_BATCH_ROWS4 | SPIN_BATCH_ROWS8))
+    const uint32_t forced = (flags >> 4) & 0xFu;
+    if ((flags & ~(SPIN_BATCH_DIRECT | 0xF0u)) || forced > (uint32_t)spin::kVariants)
         return fail(-EINVAL, "unknown flags 0x%x", flags);
     if (b->t + n > b->n_steps)
         return fail(-EINVAL, "schedule has %u steps, %llu done, %u asked", b->n_steps, (unsigned long long)b->t, n);
     if (n == 0)
         return 0;
-    if (flags & SPIN_BATCH_ROWS4)
-        b->rows = 4;
-    else if (flags & SPIN_BATCH_ROWS8)
-        b->rows = 8;
-    else if (b->rows == 0) {
+    if (forced)
+        b->variant = (int)forced - 1;
+    else if (b->variant < 0) {
         if (int rc = autotune(b))
             return rc;
     }
     if (flags & SPIN_BATCH_DIRECT) {
-        if (int rc = launch_sweeps(b, b->rows, b->t, n, b->stream))
+        if (int rc = launch_sweeps(b, b->variant, b->t, n, b->stream))
             return rc;
     } else {
         HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
@@ -321,7 +321,7 @@ int spin_batch_run(spin_batch *b, uint32_t n, uint32_t flags)
             b->graph = nullptr;
         }
         HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-        int rc = launch_sweeps(b, b->rows, b->t, n, b->stream);
+        int rc = launch_sweeps(b, b->variant, b->t, n, b->stream);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(b->stream, &g);
         if (rc) {
@@ -359,7 +359,7 @@ int spin_batch_replica(spin_batch *b, uint32_t k, spin_handle **out)
     return 0;
 }
 
-int spin_batch_info(const spin_batch *b, uint32_t *n_replicas, uint64_t *t, int *rows, uint64_t *tiles)
+int spin_batch_info(const spin_batch *b, uint32_t *n_replicas, uint64_t *t, int *variant, uint64_t *tiles)
 {
     if (!b)
         return fail(-EINVAL, "NULL batch");
@@ -367,10 +367,10 @@ int spin_batch_info(const spin_batch *b, uint32_t *n_replicas, uint64_t *t, int 
         *n_replicas = (uint32_t)b->reps.size();
     if (t)
         *t = b->t;
-    if (rows)
-        *rows = b->rows;
+    if (variant)
+        *variant = b->variant;
     if (tiles)
-        *tiles = b->rows ? b->ntiles[shape_index(b->rows)] : 0;
+        *tiles = b->variant >= 0 ? b->ntiles[shape_of(b->variant)] : 0;
     return 0;
 }
 

@@ -51,12 +51,14 @@ struct XTile {
 };
 
 // Pairs of one own word (plane C, row parity P) with all requested r.
+// Every separation of the set is computed (no per-r branch, so the LDS
+// reads pipeline); counters past the requested prefix are dropped at the end.
 template <int MODEL, int C, int P, int Q>
-__device__ __forceinline__ void x_pairs(const XTile<MODEL> &t, int k, uint32_t oz, uint32_t os, int n_r,
+__device__ __forceinline__ void x_pairs(const XTile<MODEL> &t, int k, uint32_t oz, uint32_t os,
                                         uint32_t (&ca)[kSparseN], uint32_t (&cb)[kSparseN])
 {
     if constexpr (Q < kSparseN) {
-        if (Q < n_r) {
+        {
             constexpr uint32_t r = sparse_r(Q);
             constexpr int tc = C ^ (int)(r & 1u);
             constexpr uint32_t s = (r >> 1) + ((r & 1u) & (uint32_t)P);
@@ -77,21 +79,21 @@ __device__ __forceinline__ void x_pairs(const XTile<MODEL> &t, int k, uint32_t o
                 cb[Q] += __popc(both & (os ^ bs));
             }
         }
-        x_pairs<MODEL, C, P, Q + 1>(t, k, oz, os, n_r, ca, cb);
+        x_pairs<MODEL, C, P, Q + 1>(t, k, oz, os, ca, cb);
     }
 }
 
 template <int MODEL, int C>
-__device__ __forceinline__ void x_word(const XTile<MODEL> &t, int k, uint32_t parity, int n_r,
+__device__ __forceinline__ void x_word(const XTile<MODEL> &t, int k, uint32_t parity,
                                        uint32_t (&ca)[kSparseN], uint32_t (&cb)[kSparseN])
 {
     constexpr int E = XTile<MODEL>::E;
     const uint32_t oz = MODEL == kIsing ? ~0u : t.w[C][k * E];
     const uint32_t os = t.w[C][k * E + (E - 1)];
     if (parity)
-        x_pairs<MODEL, C, 1, 0>(t, k, oz, os, n_r, ca, cb);
+        x_pairs<MODEL, C, 1, 0>(t, k, oz, os, ca, cb);
     else
-        x_pairs<MODEL, C, 0, 0>(t, k, oz, os, n_r, ca, cb);
+        x_pairs<MODEL, C, 0, 0>(t, k, oz, os, ca, cb);
 }
 
 template <int N>
@@ -140,7 +142,9 @@ __global__ __launch_bounds__(kBlock) void k_corr_x_sparse(Lattice lat, int n_r, 
         __syncthreads();
         for (int k = threadIdx.x; k < (tw + kHalo) * E; k += kBlock) {
             const int e = k / E, part = k - e * E;
-            const uint32_t wk = (w0 + (uint32_t)e) % W;
+            uint32_t wk = w0 + (uint32_t)e;
+            if (wk >= W)
+                wk = W >= kTileW + kHalo ? wk - W : wk % W;
             const size_t off = ((size_t)i * W + wk) * E + part;
             t.w[0][k] = lat.planes[off];
             t.w[1][k] = lat.planes[lat.plane_u32 + off];
@@ -148,8 +152,8 @@ __global__ __launch_bounds__(kBlock) void k_corr_x_sparse(Lattice lat, int n_r, 
         __syncthreads();
         const uint32_t p0 = i & 1u;  // row parity of colour 0; colour 1 has the other
         for (int k = threadIdx.x; k < tw; k += kBlock) {
-            x_word<MODEL, 0>(t, k, p0, n_r, ca, cb);
-            x_word<MODEL, 1>(t, k, p0 ^ 1u, n_r, ca, cb);
+            x_word<MODEL, 0>(t, k, p0, ca, cb);
+            x_word<MODEL, 1>(t, k, p0 ^ 1u, ca, cb);
         }
     }
     if (MODEL != kIsing)
@@ -170,38 +174,34 @@ struct YShape {
     static constexpr int TPR = kBlock / CH;                        // threads per chunk row
 };
 
-template <int MODEL, int Q>
+template <int MODEL, bool ALL_VALID, int Q>
 __device__ __forceinline__ void y_pairs(const uint32_t *ring, uint32_t ring_base, int jr, int col, uint32_t xe,
                                         uint32_t xo, uint32_t xse, uint32_t xso, int64_t j, uint32_t L,
-                                        bool all_valid, int n_r, uint32_t (&ca)[kSparseN],
-                                        uint32_t (&cb)[kSparseN], uint32_t RING)
+                                        uint32_t (&ca)[kSparseN], uint32_t (&cb)[kSparseN], uint32_t RING)
 {
     if constexpr (Q < kSparseN) {
-        if (Q < n_r) {
+        {
             constexpr uint32_t r = sparse_r(Q);
             // slot of base row j - r: (slot(j0) - r) mod RING + jr, mirrored past RING
             uint32_t base = ring_base + RING - (r % RING);
             if (base >= RING)
                 base -= RING;
             const int64_t i = j - (int64_t)r;
-            const bool ok = all_valid || (i >= 0 && i < (int64_t)L);
+            const bool ok = ALL_VALID || (i >= 0 && i < (int64_t)L);
             const uint32_t *row = ring + (size_t)(base + (uint32_t)jr) * kRingCols;
             if (MODEL == kIsing) {
                 const uint32_t b = row[col];
                 const uint32_t x = (r & 1u) ? xo : xe;
-                if (ok)
-                    cb[Q] += __popc(b ^ x);
+                cb[Q] += ok ? __popc(b ^ x) : 0u;
             } else {
                 const uint32_t bz = row[col], bs = row[col + 1];
                 const uint32_t xz = (r & 1u) ? xo : xe, xs = (r & 1u) ? xso : xse;
-                const uint32_t both = bz & xz;
-                if (ok) {
-                    ca[Q] += __popc(both);
-                    cb[Q] += __popc(both & (bs ^ xs));
-                }
+                const uint32_t both = ok ? (bz & xz) : 0u;
+                ca[Q] += __popc(both);
+                cb[Q] += __popc(both & (bs ^ xs));
             }
         }
-        y_pairs<MODEL, Q + 1>(ring, ring_base, jr, col, xe, xo, xse, xso, j, L, all_valid, n_r, ca, cb, RING);
+        y_pairs<MODEL, ALL_VALID, Q + 1>(ring, ring_base, jr, col, xe, xo, xse, xso, j, L, ca, cb, RING);
     }
 }
 
@@ -232,10 +232,13 @@ __global__ __launch_bounds__(kBlock) void k_corr_y_ring(Lattice lat, int n_r, ui
         ca[q] = 0;
         cb[q] = 0;
     }
+    // global loads run kDepth chunks ahead of the chunk being paired (one
+    // block per CU: the prefetch depth is what hides HBM latency)
+    constexpr int kDepth = 8;
     for (uint32_t strip = blockIdx.x; strip < strips; strip += gridDim.x) {
         const uint32_t w0 = strip * SW;
-        uint32_t pre[LPT];
-        auto load_chunk = [&](int64_t j0) {
+        uint32_t pre[kDepth][LPT];
+        auto load_chunk = [&](int64_t j0, uint32_t (&dst)[LPT]) {
 #pragma unroll
             for (int q = 0; q < LPT; ++q) {
                 const int idx = threadIdx.x + q * kBlock;  // 0 .. CH * 8 - 1
@@ -244,34 +247,47 @@ __global__ __launch_bounds__(kBlock) void k_corr_y_ring(Lattice lat, int n_r, ui
                 const uint32_t jg = (uint32_t)(j % (int64_t)L);
                 const int plane = c8 >> 2, within = c8 & 3;  // within: word (Ising) or word*2+part (BC)
                 const size_t off = ((size_t)jg * W + w0) * E + (size_t)within;
-                pre[q] = lat.planes[(plane ? lat.plane_u32 : 0) + off];
+                dst[q] = lat.planes[(plane ? lat.plane_u32 : 0) + off];
             }
         };
         __syncthreads();
-        load_chunk(0);
-        for (int64_t ch = 0; ch < nchunks; ++ch) {
-            const int64_t j0 = ch * CH;
-            const uint32_t slot0 = (uint32_t)(j0 % (int64_t)RING);  // multiple of CH
 #pragma unroll
-            for (int q = 0; q < LPT; ++q) {
-                const int idx = threadIdx.x + q * kBlock;
-                const int row = idx / kRingCols, c8 = idx % kRingCols;
-                ring[(size_t)(slot0 + row) * kRingCols + c8] = pre[q];
-                if (slot0 == 0)
-                    ring[(size_t)(RING + row) * kRingCols + c8] = pre[q];
+        for (int d = 0; d < kDepth; ++d)
+            if (d < nchunks)
+                load_chunk((int64_t)d * CH, pre[d]);
+        for (int64_t ch0 = 0; ch0 < nchunks; ch0 += kDepth) {
+#pragma unroll
+            for (int d = 0; d < kDepth; ++d) {
+                const int64_t ch = ch0 + d;
+                if (ch >= nchunks)
+                    break;
+                const int64_t j0 = ch * CH;
+                const uint32_t slot0 = (uint32_t)(j0 % (int64_t)RING);  // multiple of CH
+#pragma unroll
+                for (int q = 0; q < LPT; ++q) {
+                    const int idx = threadIdx.x + q * kBlock;
+                    const int row = idx / kRingCols, c8 = idx % kRingCols;
+                    ring[(size_t)(slot0 + row) * kRingCols + c8] = pre[d][q];
+                    if (slot0 == 0)
+                        ring[(size_t)(RING + row) * kRingCols + c8] = pre[d][q];
+                }
+                __syncthreads();
+                if (ch + kDepth < nchunks)
+                    load_chunk(j0 + (int64_t)kDepth * CH, pre[d]);
+                const int64_t j = j0 + jr;
+                const uint32_t *me = ring + (size_t)(slot0 + jr) * kRingCols;
+                const uint32_t xe = me[col], xo = me[col_other];
+                const uint32_t xse = MODEL == kIsing ? 0u : me[col + 1];
+                const uint32_t xso = MODEL == kIsing ? 0u : me[col_other + 1];
+                // every pair of the chunk is valid when j0 - r >= 0 for the largest r
+                // of the set and j0 + CH - 1 - r < L for r = 1
+                const bool all_valid = j0 >= (int64_t)sparse_r(kSparseN - 1) && j0 + CH - 1 < (int64_t)L + 1;
+                if (all_valid)
+                    y_pairs<MODEL, true, 0>(ring, slot0, jr, col, xe, xo, xse, xso, j, L, ca, cb, RING);
+                else
+                    y_pairs<MODEL, false, 0>(ring, slot0, jr, col, xe, xo, xse, xso, j, L, ca, cb, RING);
+                __syncthreads();
             }
-            __syncthreads();
-            if (ch + 1 < nchunks)
-                load_chunk(j0 + CH);
-            const int64_t j = j0 + jr;
-            const uint32_t *me = ring + (size_t)(slot0 + jr) * kRingCols;
-            const uint32_t xe = me[col], xo = me[col_other];
-            const uint32_t xse = MODEL == kIsing ? 0u : me[col + 1];
-            const uint32_t xso = MODEL == kIsing ? 0u : me[col_other + 1];
-            // every pair of the chunk is valid when j0 - r >= 0 and j0 + CH - 1 - r < L for all r
-            const bool all_valid = j0 >= (int64_t)r_max && j0 + CH - 1 < (int64_t)L + 1;
-            y_pairs<MODEL, 0>(ring, slot0, jr, col, xe, xo, xse, xso, j, L, all_valid, n_r, ca, cb, RING);
-            __syncthreads();
         }
     }
     if (MODEL != kIsing)

@@ -16,7 +16,6 @@ namespace spin {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kRows = 8;  // rows walked by one thread (vertical register reuse)
 
 // Blocks of a persistent kernel that are resident at once on the current
 // device (occupancy x compute units), so a grid-stride loop has no tail wave.
@@ -257,6 +256,60 @@ __device__ __forceinline__ void ising_tile(const Lattice &lat, uint32_t c, uint3
     __syncthreads();
 }
 
+// Ising half-sweep of one tile, one word at a time: each thread runs the
+// lazy Metropolis test of its word to completion (no queue, no LDS).
+template <bool MEASURE, int R>
+__device__ __forceinline__ void ising_tile_lazy(const Lattice &lat, uint32_t c, uint32_t t, const GroupTable &gt,
+                                                uint64_t tile, unsigned long long (&e)[kEmCounters])
+{
+    const uint32_t L = lat.L, W = lat.W;
+    uint32_t *own = lat.planes + (c ? lat.plane_u32 : 0);
+    const uint32_t *oth = lat.planes + (c ? 0 : lat.plane_u32);
+    const uint64_t nitems = (uint64_t)(L / R) * W;
+    const uint64_t g = tile * kBlock + threadIdx.x;
+    if (g >= nitems)
+        return;
+    const uint32_t thr[2] = {gt.thr[0], gt.thr[1]};
+    const bool rng3 = gt.rng_bits & 1u, rng4 = gt.rng_bits & 2u;
+    const bool nev3 = gt.never_bits & 1u, nev4 = gt.never_bits & 2u;
+    const uint32_t rg = (uint32_t)(g / W);
+    const uint32_t w = (uint32_t)(g - (uint64_t)rg * W);
+    const uint32_t i0 = rg * R;
+    const uint32_t wl = (w == 0 ? W : w) - 1u;
+    const uint32_t wr = (w + 1u == W) ? 0u : w + 1u;
+    uint32_t up = oth[(size_t)(i0 == 0 ? L - 1 : i0 - 1) * W + w];
+    uint32_t cur = oth[(size_t)i0 * W + w];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t i = i0 + (uint32_t)r;
+        const uint32_t inext = (i + 1u == L) ? 0u : i + 1u;
+        const uint32_t dn = oth[(size_t)inext * W + w];
+        const uint32_t odd = (i + c) & 1u;
+        const uint32_t side = side_word(cur, oth[(size_t)i * W + (odd ? wr : wl)], odd);
+        const size_t idx = (size_t)i * W + w;
+        const uint32_t sv = own[idx];
+        // aligned-neighbour indicators; a = number aligned, dE = J (4a - 8)
+        const uint32_t e1 = ~(sv ^ up), e2 = ~(sv ^ dn), e3 = ~(sv ^ cur), e4 = ~(sv ^ side);
+        const uint32_t a1 = e1 & e2, x1 = e1 ^ e2, a2 = e3 & e4, x2 = e3 ^ e4;
+        const uint32_t m4 = a1 & a2;                // a = 4: dE = 8J
+        const uint32_t m3 = (a1 & x2) | (a2 & x1);  // a = 3: dE = 4J
+        const uint32_t need[2] = {rng3 ? m3 : 0u, rng4 ? m4 : 0u};
+        const uint32_t never = (nev3 ? m3 : 0u) | (nev4 ? m4 : 0u);
+        const uint32_t always = ~(need[0] | need[1] | never);
+        const uint32_t flip = metropolis_accept<2>(need, thr, always, i, w, t, c, lat.key0, lat.key1);
+        const uint32_t ns = sv ^ flip;
+        own[idx] = ns;
+        if (MEASURE) {
+            e[0] += 64;
+            e[1] += __popc(ns) + __popc(cur);
+            e[2] += 128;
+            e[3] += __popc(ns ^ up) + __popc(ns ^ dn) + __popc(ns ^ cur) + __popc(ns ^ side);
+        }
+        up = cur;
+        cur = dn;
+    }
+}
+
 struct Pair {
     uint32_t z, s;  // z: s != 0, s: s < 0
 };
@@ -383,31 +436,38 @@ __host__ __device__ inline uint64_t tiles_of(const Lattice &lat)
     return ((uint64_t)(lat.L / R) * lat.W + kBlock - 1) / kBlock;
 }
 
-template <bool MEASURE>
+template <bool MEASURE, int V>
 __global__ __launch_bounds__(kBlock) void k_sweep_ising(Lattice lat, uint32_t c, uint32_t t, GroupTable gt,
                                                         unsigned long long *acc)
 {
-    __shared__ IsingQueue<kRows> Q;
+    constexpr int R = variant_rows(V);
     unsigned long long e[kEmCounters] = {0, 0, 0, 0};
-    const uint64_t ntiles = tiles_of<kRows>(lat);
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-        ising_tile<MEASURE, kRows>(lat, c, t, gt, tile, Q, e);
+    const uint64_t ntiles = tiles_of<R>(lat);
+    if constexpr (variant_queue(V)) {
+        __shared__ IsingQueue<R> Q;
+        for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+            ising_tile<MEASURE, R>(lat, c, t, gt, tile, Q, e);
+    } else {
+        for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+            ising_tile_lazy<MEASURE, R>(lat, c, t, gt, tile, e);
+    }
     if (MEASURE)
         block_reduce_atomic<kEmCounters>(e, acc);
 }
 
-template <bool MEASURE>
+template <bool MEASURE, int V>
 __global__ __launch_bounds__(kBlock) void k_sweep_bc(Lattice lat, uint32_t c, uint32_t t, GroupTable gt,
                                                      unsigned long long *acc)
 {
+    constexpr int R = variant_rows(V);
     unsigned long long e[kEmCounters] = {0, 0, 0, 0};
-    const uint64_t ntiles = tiles_of<kRows>(lat);
+    const uint64_t ntiles = tiles_of<R>(lat);
     if (lat.bc_groups == kBcGroupsDelta0) {
         for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-            bc_tile<MEASURE, kRows, kBcGroupsDelta0>(lat, c, t, gt, tile, e);
+            bc_tile<MEASURE, R, kBcGroupsDelta0>(lat, c, t, gt, tile, e);
     } else {
         for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-            bc_tile<MEASURE, kRows, kBcGroups>(lat, c, t, gt, tile, e);
+            bc_tile<MEASURE, R, kBcGroups>(lat, c, t, gt, tile, e);
     }
     if (MEASURE)
         block_reduce_atomic<kEmCounters>(e, acc);
@@ -417,12 +477,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep_bc(Lattice lat, uint32_t c, ui
 // flat tile list maps each global tile to (replica, local tile); replica r's
 // thresholds for this sweep are tables[sched(r) * stride + step] and its
 // random stream runs at sweep index t0(r) + step.
-template <int R>
+template <int V>
 __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica *reps, const uint32_t *tile_rep,
                                                              uint64_t ntiles, const GroupTable *tables,
                                                              uint32_t stride, uint32_t step, uint32_t c)
 {
-    __shared__ IsingQueue<R> Q;
+    constexpr int R = variant_rows(V);
+    __shared__ IsingQueue<variant_queue(V) ? R : 1> Q;
     unsigned long long e[kEmCounters] = {0, 0, 0, 0};
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const uint32_t rid = tile_rep[tile];
@@ -430,9 +491,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica 
         const GroupTable &gt = tables[(size_t)rep.sched * stride + step];
         const uint64_t local = tile - rep.tile0;
         const uint32_t t = rep.t0 + step;
-        if (rep.lat.model == kIsing)
-            ising_tile<false, R>(rep.lat, c, t, gt, local, Q, e);
-        else if (rep.lat.bc_groups == kBcGroupsDelta0)
+        if (rep.lat.model == kIsing) {
+            if constexpr (variant_queue(V))
+                ising_tile<false, R>(rep.lat, c, t, gt, local, Q, e);
+            else
+                ising_tile_lazy<false, R>(rep.lat, c, t, gt, local, e);
+        } else if (rep.lat.bc_groups == kBcGroupsDelta0)
             bc_tile<false, R, kBcGroupsDelta0>(rep.lat, c, t, gt, local, e);
         else
             bc_tile<false, R, kBcGroups>(rep.lat, c, t, gt, local, e);
@@ -618,33 +682,40 @@ hipError_t launch_init(const Lattice &lat, hipStream_t st)
     return hipGetLastError();
 }
 
+template <bool M, int V>
+hipError_t launch_half_sweep_v(const Lattice &lat, uint32_t colour, uint32_t t, const GroupTable &gt,
+                               unsigned long long *em_acc, hipStream_t st)
+{
+    constexpr int R = variant_rows(V);
+    const uint64_t tiles = tiles_of<R>(lat);
+    const dim3 block(kBlock);
+    if (lat.model == kIsing) {
+        static const unsigned g = resident_grid(k_sweep_ising<M, V>, 0, ~0ull);
+        hipLaunchKernelGGL((k_sweep_ising<M, V>), dim3(g < tiles ? g : (unsigned)tiles), block, 0, st, lat, colour,
+                           t, gt, em_acc);
+    } else {
+        static const unsigned g = resident_grid(k_sweep_bc<M, V>, 0, ~0ull);
+        hipLaunchKernelGGL((k_sweep_bc<M, V>), dim3(g < tiles ? g : (unsigned)tiles), block, 0, st, lat, colour, t,
+                           gt, em_acc);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_half_sweep(const Lattice &lat, uint32_t colour, uint32_t t, const GroupTable &gt,
                              unsigned long long *em_acc, hipStream_t st)
 {
-    const uint64_t tiles = tiles_of<kRows>(lat);
-    const dim3 block(kBlock);
-    if (lat.model == kIsing) {
-        if (em_acc) {
-            static const unsigned g = resident_grid(k_sweep_ising<true>, 0, ~0ull);
-            hipLaunchKernelGGL(k_sweep_ising<true>, dim3(g < tiles ? g : (unsigned)tiles), block, 0, st, lat,
-                               colour, t, gt, em_acc);
-        } else {
-            static const unsigned g = resident_grid(k_sweep_ising<false>, 0, ~0ull);
-            hipLaunchKernelGGL(k_sweep_ising<false>, dim3(g < tiles ? g : (unsigned)tiles), block, 0, st, lat,
-                               colour, t, gt, em_acc);
-        }
-    } else {
-        if (em_acc) {
-            static const unsigned g = resident_grid(k_sweep_bc<true>, 0, ~0ull);
-            hipLaunchKernelGGL(k_sweep_bc<true>, dim3(g < tiles ? g : (unsigned)tiles), block, 0, st, lat, colour,
-                               t, gt, em_acc);
-        } else {
-            static const unsigned g = resident_grid(k_sweep_bc<false>, 0, ~0ull);
-            hipLaunchKernelGGL(k_sweep_bc<false>, dim3(g < tiles ? g : (unsigned)tiles), block, 0, st, lat,
-                               colour, t, gt, em_acc);
-        }
+    const bool m = em_acc != nullptr;
+    switch (lat.variant) {
+    case 0: return m ? launch_half_sweep_v<true, 0>(lat, colour, t, gt, em_acc, st)
+                     : launch_half_sweep_v<false, 0>(lat, colour, t, gt, em_acc, st);
+    case 1: return m ? launch_half_sweep_v<true, 1>(lat, colour, t, gt, em_acc, st)
+                     : launch_half_sweep_v<false, 1>(lat, colour, t, gt, em_acc, st);
+    case 2: return m ? launch_half_sweep_v<true, 2>(lat, colour, t, gt, em_acc, st)
+                     : launch_half_sweep_v<false, 2>(lat, colour, t, gt, em_acc, st);
+    case 3: return m ? launch_half_sweep_v<true, 3>(lat, colour, t, gt, em_acc, st)
+                     : launch_half_sweep_v<false, 3>(lat, colour, t, gt, em_acc, st);
+    default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 uint64_t sweep_tiles(const Lattice &lat, int rows)
@@ -652,22 +723,27 @@ uint64_t sweep_tiles(const Lattice &lat, int rows)
     return rows == 4 ? tiles_of<4>(lat) : tiles_of<8>(lat);
 }
 
-hipError_t launch_batch_half_sweep(int rows, const BatchReplica *reps, const uint32_t *tile_rep, uint64_t ntiles,
-                                   const GroupTable *tables, uint32_t stride, uint32_t step, uint32_t colour,
-                                   hipStream_t st)
+template <int V>
+hipError_t launch_batch_v(const BatchReplica *reps, const uint32_t *tile_rep, uint64_t ntiles,
+                          const GroupTable *tables, uint32_t stride, uint32_t step, uint32_t colour, hipStream_t st)
 {
-    if (rows == 4) {
-        static const unsigned g = resident_grid(k_batch_half_sweep<4>, 0, ~0ull);
-        hipLaunchKernelGGL(k_batch_half_sweep<4>, dim3(g < ntiles ? g : (unsigned)ntiles), dim3(kBlock), 0, st,
-                           reps, tile_rep, ntiles, tables, stride, step, colour);
-    } else if (rows == 8) {
-        static const unsigned g = resident_grid(k_batch_half_sweep<8>, 0, ~0ull);
-        hipLaunchKernelGGL(k_batch_half_sweep<8>, dim3(g < ntiles ? g : (unsigned)ntiles), dim3(kBlock), 0, st,
-                           reps, tile_rep, ntiles, tables, stride, step, colour);
-    } else {
-        return hipErrorInvalidValue;
-    }
+    static const unsigned g = resident_grid(k_batch_half_sweep<V>, 0, ~0ull);
+    hipLaunchKernelGGL(k_batch_half_sweep<V>, dim3(g < ntiles ? g : (unsigned)ntiles), dim3(kBlock), 0, st, reps,
+                       tile_rep, ntiles, tables, stride, step, colour);
     return hipGetLastError();
+}
+
+hipError_t launch_batch_half_sweep(int variant, const BatchReplica *reps, const uint32_t *tile_rep,
+                                   uint64_t ntiles, const GroupTable *tables, uint32_t stride, uint32_t step,
+                                   uint32_t colour, hipStream_t st)
+{
+    switch (variant) {
+    case 0: return launch_batch_v<0>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
+    case 1: return launch_batch_v<1>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
+    case 2: return launch_batch_v<2>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
+    case 3: return launch_batch_v<3>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_measure_em(const Lattice &lat, unsigned long long *em_acc, hipStream_t st)

@@ -35,7 +35,16 @@ struct Lattice {
     int model;
     uint32_t key0, key1;
     uint32_t bc_groups;  // Blume-Capel acceptance groups in use: 13, or 6 when Delta = 0
+    int variant;         // sweep strategy, see variant_rows / variant_queue
 };
+
+// Sweep strategies: rows walked per thread (4 or 8) and, for Ising, whether
+// undecided words go through the block's LDS work queue (ising_tile) or each
+// thread finishes its word's lazy test itself (ising_tile_lazy).
+//   0: 8 rows, per word   1: 4 rows, queue   2: 8 rows, queue   3: 4 rows, per word
+constexpr int kVariants = 4;
+__host__ __device__ constexpr int variant_rows(int v) { return (v == 1 || v == 3) ? 4 : 8; }
+__host__ __device__ constexpr bool variant_queue(int v) { return v == 1 || v == 2; }
 
 // Counters of the energy/magnetisation reduction (both colours):
 //   acc[0] = #(s != 0)  acc[1] = #(s < 0)
@@ -56,11 +65,10 @@ hipError_t launch_init(const Lattice &lat, hipStream_t st);
 // Sweep work units (tiles of 256 word columns x rows) of one lattice for a
 // rows-per-thread choice (4 or 8), and the batched half-sweep over a flat
 // tile list of many lattices.
-constexpr int kBatchRowChoices[2] = {4, 8};
 uint64_t sweep_tiles(const Lattice &lat, int rows);
-hipError_t launch_batch_half_sweep(int rows, const BatchReplica *reps, const uint32_t *tile_rep, uint64_t ntiles,
-                                   const GroupTable *tables, uint32_t stride, uint32_t step, uint32_t colour,
-                                   hipStream_t st);
+hipError_t launch_batch_half_sweep(int variant, const BatchReplica *reps, const uint32_t *tile_rep,
+                                   uint64_t ntiles, const GroupTable *tables, uint32_t stride, uint32_t step,
+                                   uint32_t colour, hipStream_t st);
 hipError_t launch_half_sweep(const Lattice &lat, uint32_t colour, uint32_t t, const GroupTable &gt,
                              unsigned long long *em_acc, hipStream_t st);
 hipError_t launch_measure_em(const Lattice &lat, unsigned long long *em_acc, hipStream_t st);

@@ -261,6 +261,7 @@ int spin_create(int model, uint32_t L, uint64_t seed, double J, double Delta, vo
     h->lat.model = model;
     h->lat.key0 = (uint32_t)seed;
     h->lat.key1 = (uint32_t)(seed >> 32);
+    h->lat.variant = 0;
     h->lat.bc_groups = spin::kBcGroups;
     {
         // merged groups need every member to give the same dE; that does not
@@ -515,6 +516,88 @@ int spin_get_t(const spin_handle *h, uint64_t *t)
     if (!t)
         return fail(-EINVAL, "NULL output");
     *t = h->t;
+    return 0;
+}
+
+int spin_set_variant(spin_handle *h, int variant)
+{
+    if (int rc = check_handle(h))
+        return rc;
+    if (variant < 0 || variant >= spin::kVariants)
+        return fail(-EINVAL, "variant %d outside 0..%d", variant, spin::kVariants - 1);
+    h->lat.variant = variant;
+    return 0;
+}
+
+int spin_get_variant(const spin_handle *h, int *variant)
+{
+    if (int rc = check_handle(h))
+        return rc;
+    if (!variant)
+        return fail(-EINVAL, "NULL output");
+    *variant = h->lat.variant;
+    return 0;
+}
+
+int spin_tune(spin_handle *h, double T, int *chosen)
+{
+    if (int rc = check_handle(h))
+        return rc;
+    if (!(T >= 0.0))
+        return fail(-EINVAL, "T must be >= 0");
+    const uint32_t Ls = h->L < 16384u ? h->L : 16384u;
+    const int64_t bytes = spin_lattice_bytes(h->model, Ls);
+    void *scratch = nullptr;
+    hipError_t e = hipMalloc(&scratch, (size_t)bytes);
+    if (e != hipSuccess)
+        return fail(-ENOMEM, "tuning scratch of %lld bytes: %s", (long long)bytes, hipGetErrorString(e));
+    spin::Lattice lat = h->lat;
+    lat.planes = (uint32_t *)scratch;
+    lat.L = Ls;
+    lat.W = Ls / 64;
+    lat.plane_u32 = (uint64_t)Ls * lat.W * (h->model == SPIN_ISING ? 1 : 2);
+    const GroupTable gt = make_groups(h->model, lat.bc_groups, h->J, h->Delta, T);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = 0;
+    float best_ms = -1.0f;
+    int best = h->lat.variant;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        rc = fail(-EIO, "hipEventCreate failed");
+    for (int v = 0; v < spin::kVariants && rc == 0; ++v) {
+        lat.variant = v;
+        hipError_t err = spin::launch_init(lat, h->stream);
+        for (uint32_t k = 0; k < 6 && err == hipSuccess; ++k) {  // 1 sweep warm-up, 2 timed
+            if (k == 2)
+                err = hipEventRecord(e0, h->stream);
+            if (err == hipSuccess)
+                err = spin::launch_half_sweep(lat, k & 1u, k >> 1, gt, nullptr, h->stream);
+        }
+        if (err == hipSuccess)
+            err = hipEventRecord(e1, h->stream);
+        if (err == hipSuccess)
+            err = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (err == hipSuccess)
+            err = hipEventElapsedTime(&ms, e0, e1);
+        if (err != hipSuccess) {
+            rc = hip_fail(err, "tuning sweep");
+            break;
+        }
+        if (best_ms < 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    (void)hipFree(scratch);
+    if (rc)
+        return rc;
+    h->lat.variant = best;
+    if (chosen)
+        *chosen = best;
     return 0;
 }
 

@@ -23,7 +23,7 @@ from collections import deque
 
 import numpy as np
 
-from . import (BATCH_ROWS8, spin_batch_create, spin_batch_destroy, spin_batch_run, spin_create,
+from . import (BATCH_VARIANT, spin_batch_create, spin_batch_destroy, spin_batch_run, spin_create,
                spin_destroy, spin_get_spins, spin_init_random, spin_lattice_bytes, spin_measure,
                spin_replica_desc, spin_set_t)
 from . import workloads
@@ -46,9 +46,10 @@ class Job:
 class GpuBackend:
     """Lattices in torch device buffers; one spin_batch per epoch."""
 
-    def __init__(self, device="cuda"):
+    def __init__(self, device="cuda", variant=0):
         import torch
         self.torch = torch
+        self.variant = variant  # sweep strategy of every epoch (no per-epoch tuning)
         self.device = torch.device(device)
         self.stream = torch.cuda.Stream(self.device)
 
@@ -71,7 +72,7 @@ class GpuBackend:
                                    temps.index(j.T), j.done) for j in jobs]
         b = spin_batch_create(descs, T, self.stream.cuda_stream)
         try:
-            spin_batch_run(b, n, BATCH_ROWS8)
+            spin_batch_run(b, n, BATCH_VARIANT(self.variant))
         finally:
             spin_batch_destroy(b)  # waits for the epoch's work
 

@@ -205,6 +205,32 @@ def test_sparse_and_generic_correlation_kernels_agree(gpu, model, L):
     lat.close()
 
 
+@pytest.mark.parametrize("model", [0, 1])
+def test_sweep_strategies_agree(gpu, model):
+    """All sweep strategies (rows per thread, per-word or queued random
+    planes) give the oracle's trajectory; the tuner picks one of them."""
+    L, seed = 512, 77
+    T = np.full(6, 2.2 if model == 0 else 1.7)
+    s = oracle.init(model, L, seed)
+    oracle.sweep(model, s, seed, 1.0, 0.0, 0, T)
+    bond = oracle.measure(s, [])["bond"]
+    for v in range(4):
+        lat = make(gpu, model, L, seed)
+        lat.variant = v
+        assert lat.variant == v
+        lat.sweep(T, fuse_measure=True)
+        assert np.array_equal(lat.spins(), s), v
+        assert lat.measure()["bond"] == bond
+        lat.close()
+    lat = make(gpu, model, L, seed)
+    assert lat.tune(float(T[0])) in (0, 1, 2, 3)
+    lat.sweep(T)
+    assert np.array_equal(lat.spins(), s)
+    with pytest.raises(gpu.SpinError):
+        lat.variant = 4
+    lat.close()
+
+
 def test_ising_L4096_check_run(gpu):
     """The bit-exact check lattice of the large Ising workload: 2^12 x 2^12, 64 sweeps."""
     w = workloads.ISING_CHECK
