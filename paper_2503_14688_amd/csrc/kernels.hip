@@ -689,12 +689,16 @@ hipError_t launch_half_sweep_v(const Lattice &lat, uint32_t colour, uint32_t t, 
     constexpr int R = variant_rows(V);
     const uint64_t tiles = tiles_of<R>(lat);
     const dim3 block(kBlock);
+    // per-word strategies: many more blocks than fit at once (the hardware
+    // keeps every CU full); queued strategies hold LDS state per block and use
+    // exactly the resident number of blocks
     if (lat.model == kIsing) {
-        static const unsigned g = resident_grid(k_sweep_ising<M, V>, 0, ~0ull);
+        static const unsigned g =
+            variant_queue(V) ? resident_grid(k_sweep_ising<M, V>, 0, ~0ull) : 65536u;
         hipLaunchKernelGGL((k_sweep_ising<M, V>), dim3(g < tiles ? g : (unsigned)tiles), block, 0, st, lat, colour,
                            t, gt, em_acc);
     } else {
-        static const unsigned g = resident_grid(k_sweep_bc<M, V>, 0, ~0ull);
+        static const unsigned g = 65536u;
         hipLaunchKernelGGL((k_sweep_bc<M, V>), dim3(g < tiles ? g : (unsigned)tiles), block, 0, st, lat, colour, t,
                            gt, em_acc);
     }
