@@ -10,7 +10,7 @@
 //
 // Vertical (k_corr_y_ring): a block owns a 4-word (Ising) or 2-word
 // (Blume-Capel) column strip of both planes and walks down the lattice once,
-// keeping the last r_max + chunk rows in an LDS ring; each new row meets its
+// keeping the last r_max + 256 rows in an LDS ring; each new row meets its
 // 48 partners above it in the ring, so the lattice is read from HBM about
 // once for all separations.
 #include "device.hpp"
@@ -163,45 +163,69 @@ __global__ __launch_bounds__(kBlock) void k_corr_x_sparse(Lattice lat, int n_r, 
 
 // -------------------------------------------------------------- vertical --
 
-// A ring row is 8 uint32: Ising words [w0, w0 + 4) of plane 0 then plane 1;
-// Blume-Capel (Z, S) of words [w0, w0 + 2) of plane 0 then plane 1.
+// A ring row is 8 uint32 (32 bytes): Ising words [w0, w0 + 4) of plane 0 then
+// plane 1; Blume-Capel (Z, S) of words [w0, w0 + 2) of plane 0 then plane 1.
+// Thread jr of a block owns ring row j0 + jr of every chunk: it reads its own
+// row once and, for each separation, the row r above it with two 16-byte
+// LDS loads, pairing all 8 words at once.
 constexpr int kRingCols = 8;
+constexpr int kChunk = kBlock;  // ring rows per chunk, one per thread
 
 template <int MODEL>
 struct YShape {
-    static constexpr int CH = MODEL == kIsing ? 32 : 64;          // rows per chunk
-    static constexpr int SW = MODEL == kIsing ? 4 : 2;            // words per plane in the strip
-    static constexpr int TPR = kBlock / CH;                        // threads per chunk row
+    static constexpr int SW = MODEL == kIsing ? 4 : 2;  // words per plane in the strip
 };
 
+struct Row8 {
+    uint32_t v[8];
+};
+
+__device__ __forceinline__ Row8 lds_row(const uint32_t *ring, uint32_t slot)
+{
+    const uint4 *p = reinterpret_cast<const uint4 *>(ring + (size_t)slot * kRingCols);
+    const uint4 a = p[0], b = p[1];
+    Row8 r;
+    r.v[0] = a.x; r.v[1] = a.y; r.v[2] = a.z; r.v[3] = a.w;
+    r.v[4] = b.x; r.v[5] = b.y; r.v[6] = b.z; r.v[7] = b.w;
+    return r;
+}
+
+// Pairs of the thread's partner row x (row j) with the base row j - r for
+// every r of the set.  Base plane c, partner plane c ^ (r & 1), same words.
 template <int MODEL, bool ALL_VALID, int Q>
-__device__ __forceinline__ void y_pairs(const uint32_t *ring, uint32_t ring_base, int jr, int col, uint32_t xe,
-                                        uint32_t xo, uint32_t xse, uint32_t xso, int64_t j, uint32_t L,
-                                        uint32_t (&ca)[kSparseN], uint32_t (&cb)[kSparseN], uint32_t RING)
+__device__ __forceinline__ void y_pairs(const uint32_t *ring, uint32_t slot0, int jr, const Row8 &x, int64_t j,
+                                        uint32_t L, uint32_t RING, uint32_t (&ca)[kSparseN],
+                                        uint32_t (&cb)[kSparseN])
 {
     if constexpr (Q < kSparseN) {
         {
             constexpr uint32_t r = sparse_r(Q);
-            // slot of base row j - r: (slot(j0) - r) mod RING + jr, mirrored past RING
-            uint32_t base = ring_base + RING - (r % RING);
+            constexpr int flip = (r & 1u) ? 4 : 0;  // partner column of base column k: k ^ flip
+            uint32_t base = slot0 + RING - (r % RING);
             if (base >= RING)
                 base -= RING;
+            const Row8 b = lds_row(ring, base + (uint32_t)jr);  // mirrored past RING
             const int64_t i = j - (int64_t)r;
             const bool ok = ALL_VALID || (i >= 0 && i < (int64_t)L);
-            const uint32_t *row = ring + (size_t)(base + (uint32_t)jr) * kRingCols;
-            if (MODEL == kIsing) {
-                const uint32_t b = row[col];
-                const uint32_t x = (r & 1u) ? xo : xe;
-                cb[Q] += ok ? __popc(b ^ x) : 0u;
+            if constexpr (MODEL == kIsing) {
+                uint32_t n = 0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    n += __popc(b.v[k] ^ x.v[k ^ flip]);
+                cb[Q] += ok ? n : 0u;
             } else {
-                const uint32_t bz = row[col], bs = row[col + 1];
-                const uint32_t xz = (r & 1u) ? xo : xe, xs = (r & 1u) ? xso : xse;
-                const uint32_t both = ok ? (bz & xz) : 0u;
-                ca[Q] += __popc(both);
-                cb[Q] += __popc(both & (bs ^ xs));
+                uint32_t na = 0, nb = 0;
+#pragma unroll
+                for (int k = 0; k < 8; k += 2) {
+                    const uint32_t both = b.v[k] & x.v[k ^ flip];
+                    na += __popc(both);
+                    nb += __popc(both & (b.v[k + 1] ^ x.v[(k ^ flip) + 1]));
+                }
+                ca[Q] += ok ? na : 0u;
+                cb[Q] += ok ? nb : 0u;
             }
         }
-        y_pairs<MODEL, ALL_VALID, Q + 1>(ring, ring_base, jr, col, xe, xo, xse, xso, j, L, ca, cb, RING);
+        y_pairs<MODEL, ALL_VALID, Q + 1>(ring, slot0, jr, x, j, L, RING, ca, cb);
     }
 }
 
@@ -209,85 +233,57 @@ template <int MODEL>
 __global__ __launch_bounds__(kBlock) void k_corr_y_ring(Lattice lat, int n_r, uint32_t RING,
                                                         unsigned long long *acc)
 {
-    extern __shared__ uint32_t ring[];  // (RING + CH) rows of kRingCols words
-    using S = YShape<MODEL>;
-    constexpr int CH = S::CH, SW = S::SW;
+    extern __shared__ uint32_t ring[];  // (RING + kChunk) rows of kRingCols words
+    constexpr int SW = YShape<MODEL>::SW;
     constexpr int E = MODEL == kIsing ? 1 : 2;
     const uint32_t L = lat.L, W = lat.W;
     const uint32_t strips = W / SW;
     const uint32_t r_max = sparse_r(n_r - 1);
     const int64_t rows_total = (int64_t)L + r_max;  // partner rows j = 0 .. L + r_max - 1
-    const int64_t nchunks = (rows_total + CH - 1) / CH;
-    // loading: CH rows x 8 words, LPT words per thread
-    constexpr int LPT = CH * kRingCols / kBlock;
-    // compute: thread -> (chunk row jr, column); Ising one word column, BC one (Z,S) column
-    const int jr = threadIdx.x / S::TPR;
-    const int lane_col = threadIdx.x % S::TPR;           // Ising 0..7, BC 0..3
-    const int col = MODEL == kIsing ? lane_col : 2 * lane_col;  // ring column of the base word
-    // partner column in the other plane: columns 0..3 are plane 0, 4..7 plane 1
-    const int col_other = col ^ 4;
+    const int64_t nchunks = (rows_total + kChunk - 1) / kChunk;
+    const int jr = threadIdx.x;
     uint32_t ca[kSparseN], cb[kSparseN];
 #pragma unroll
     for (int q = 0; q < kSparseN; ++q) {
         ca[q] = 0;
         cb[q] = 0;
     }
-    // global loads run kDepth chunks ahead of the chunk being paired (one
-    // block per CU: the prefetch depth is what hides HBM latency)
-    constexpr int kDepth = 8;
+    // global loads run one chunk ahead of the chunk being paired
     for (uint32_t strip = blockIdx.x; strip < strips; strip += gridDim.x) {
         const uint32_t w0 = strip * SW;
-        uint32_t pre[kDepth][LPT];
-        auto load_chunk = [&](int64_t j0, uint32_t (&dst)[LPT]) {
-#pragma unroll
-            for (int q = 0; q < LPT; ++q) {
-                const int idx = threadIdx.x + q * kBlock;  // 0 .. CH * 8 - 1
-                const int row = idx / kRingCols, c8 = idx % kRingCols;
-                const int64_t j = j0 + row;
-                const uint32_t jg = (uint32_t)(j % (int64_t)L);
-                const int plane = c8 >> 2, within = c8 & 3;  // within: word (Ising) or word*2+part (BC)
-                const size_t off = ((size_t)jg * W + w0) * E + (size_t)within;
-                dst[q] = lat.planes[(plane ? lat.plane_u32 : 0) + off];
-            }
+        auto load_row = [&](int64_t j, uint4 &p0, uint4 &p1) {
+            const uint32_t jg = (uint32_t)(j % (int64_t)L);
+            const size_t off = ((size_t)jg * W + w0) * E;  // 16 bytes per plane
+            p0 = *reinterpret_cast<const uint4 *>(lat.planes + off);
+            p1 = *reinterpret_cast<const uint4 *>(lat.planes + lat.plane_u32 + off);
         };
+        uint4 n0, n1;
         __syncthreads();
-#pragma unroll
-        for (int d = 0; d < kDepth; ++d)
-            if (d < nchunks)
-                load_chunk((int64_t)d * CH, pre[d]);
-        for (int64_t ch0 = 0; ch0 < nchunks; ch0 += kDepth) {
-#pragma unroll
-            for (int d = 0; d < kDepth; ++d) {
-                const int64_t ch = ch0 + d;
-                if (ch >= nchunks)
-                    break;
-                const int64_t j0 = ch * CH;
-                const uint32_t slot0 = (uint32_t)(j0 % (int64_t)RING);  // multiple of CH
-#pragma unroll
-                for (int q = 0; q < LPT; ++q) {
-                    const int idx = threadIdx.x + q * kBlock;
-                    const int row = idx / kRingCols, c8 = idx % kRingCols;
-                    ring[(size_t)(slot0 + row) * kRingCols + c8] = pre[d][q];
-                    if (slot0 == 0)
-                        ring[(size_t)(RING + row) * kRingCols + c8] = pre[d][q];
-                }
-                __syncthreads();
-                if (ch + kDepth < nchunks)
-                    load_chunk(j0 + (int64_t)kDepth * CH, pre[d]);
-                const int64_t j = j0 + jr;
-                const uint32_t *me = ring + (size_t)(slot0 + jr) * kRingCols;
-                const uint32_t xe = me[col], xo = me[col_other];
-                const uint32_t xse = MODEL == kIsing ? 0u : me[col + 1];
-                const uint32_t xso = MODEL == kIsing ? 0u : me[col_other + 1];
-                // every pair of the chunk is valid when j0 - r >= 0 for the largest r
-                // of the set and j0 + CH - 1 - r < L for r = 1
-                const bool all_valid = j0 >= (int64_t)sparse_r(kSparseN - 1) && j0 + CH - 1 < (int64_t)L + 1;
-                if (all_valid)
-                    y_pairs<MODEL, true, 0>(ring, slot0, jr, col, xe, xo, xse, xso, j, L, ca, cb, RING);
-                else
-                    y_pairs<MODEL, false, 0>(ring, slot0, jr, col, xe, xo, xse, xso, j, L, ca, cb, RING);
-                __syncthreads();
+        load_row(jr, n0, n1);
+        for (int64_t ch = 0; ch < nchunks; ++ch) {
+            const int64_t j0 = ch * kChunk;
+            const uint32_t slot0 = (uint32_t)(j0 % (int64_t)RING);  // multiple of kChunk
+            uint4 *dst = reinterpret_cast<uint4 *>(ring + (size_t)(slot0 + jr) * kRingCols);
+            dst[0] = n0;
+            dst[1] = n1;
+            if (slot0 == 0) {
+                uint4 *mir = reinterpret_cast<uint4 *>(ring + (size_t)(RING + jr) * kRingCols);
+                mir[0] = n0;
+                mir[1] = n1;
             }
+            __syncthreads();
+            if (ch + 1 < nchunks)
+                load_row(j0 + kChunk + jr, n0, n1);
+            const int64_t j = j0 + jr;
+            const Row8 x = lds_row(ring, slot0 + (uint32_t)jr);
+            // every pair of the chunk is valid when j0 - r >= 0 for the largest r
+            // of the set and j0 + kChunk - 1 - r < L for r = 1
+            const bool all_valid = j0 >= (int64_t)sparse_r(kSparseN - 1) && j0 + kChunk - 1 < (int64_t)L + 1;
+            if (all_valid)
+                y_pairs<MODEL, true, 0>(ring, slot0, jr, x, j, L, RING, ca, cb);
+            else
+                y_pairs<MODEL, false, 0>(ring, slot0, jr, x, j, L, RING, ca, cb);
+            __syncthreads();
         }
     }
     if (MODEL != kIsing)
@@ -337,18 +333,14 @@ hipError_t launch_corr_sparse(const Lattice &lat, bool vertical, int n_r, unsign
         return hipGetLastError();
     }
     const uint32_t r_max = sparse_r(n_r - 1);
+    const uint32_t RING = (r_max + kChunk + kChunk - 1) / kChunk * kChunk;
+    const size_t lds = (size_t)(RING + kChunk) * kRingCols * sizeof(uint32_t);
     if (lat.model == kIsing) {
-        constexpr int CH = YShape<kIsing>::CH;
-        const uint32_t RING = (r_max + CH + CH - 1) / CH * CH;
-        const size_t lds = (size_t)(RING + CH) * kRingCols * sizeof(uint32_t);
         const dim3 grid(corr_grid(lat.W / YShape<kIsing>::SW, 256)), block(kBlock);
         (void)hipFuncSetAttribute((const void *)k_corr_y_ring<kIsing>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(k_corr_y_ring<kIsing>, grid, block, lds, st, lat, n_r, RING, acc);
     } else {
-        constexpr int CH = YShape<kBlumeCapel>::CH;
-        const uint32_t RING = (r_max + CH + CH - 1) / CH * CH;
-        const size_t lds = (size_t)(RING + CH) * kRingCols * sizeof(uint32_t);
         const dim3 grid(corr_grid(lat.W / YShape<kBlumeCapel>::SW, 256)), block(kBlock);
         (void)hipFuncSetAttribute((const void *)k_corr_y_ring<kBlumeCapel>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -359,10 +351,10 @@ hipError_t launch_corr_sparse(const Lattice &lat, bool vertical, int n_r, unsign
 
 size_t corr_sparse_y_lds(const Lattice &lat, int n_r)
 {
-    const int CH = lat.model == kIsing ? YShape<kIsing>::CH : YShape<kBlumeCapel>::CH;
+    (void)lat;
     const uint32_t r_max = sparse_r(n_r - 1);
-    const uint32_t RING = (r_max + CH + CH - 1) / CH * CH;
-    return (size_t)(RING + CH) * kRingCols * sizeof(uint32_t);
+    const uint32_t RING = (r_max + kChunk + kChunk - 1) / kChunk * kChunk;
+    return (size_t)(RING + kChunk) * kRingCols * sizeof(uint32_t);
 }
 
 } // namespace spin
