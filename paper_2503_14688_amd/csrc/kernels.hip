@@ -258,7 +258,10 @@ __device__ __forceinline__ void ising_tile(const Lattice &lat, uint32_t c, uint3
 
 // Ising half-sweep of one tile, one word at a time: each thread runs the
 // lazy Metropolis test of its word to completion (no queue, no LDS).
-template <bool MEASURE, int R>
+// UNIFORM: W is a multiple of kBlock, so the block's 256 items share one row
+// group; the row index is then wave-uniform and the counter words that
+// depend only on it and on t start the Philox rounds in scalar registers.
+template <bool MEASURE, int R, bool UNIFORM>
 __device__ __forceinline__ void ising_tile_lazy(const Lattice &lat, uint32_t c, uint32_t t, const GroupTable &gt,
                                                 uint64_t tile, unsigned long long (&e)[kEmCounters])
 {
@@ -272,8 +275,14 @@ __device__ __forceinline__ void ising_tile_lazy(const Lattice &lat, uint32_t c, 
     const uint32_t thr[2] = {gt.thr[0], gt.thr[1]};
     const bool rng3 = gt.rng_bits & 1u, rng4 = gt.rng_bits & 2u;
     const bool nev3 = gt.never_bits & 1u, nev4 = gt.never_bits & 2u;
-    const uint32_t rg = (uint32_t)(g / W);
-    const uint32_t w = (uint32_t)(g - (uint64_t)rg * W);
+    uint32_t rg, w;
+    if (UNIFORM) {
+        rg = __builtin_amdgcn_readfirstlane((uint32_t)((tile * kBlock) / W));
+        w = (uint32_t)(g - (uint64_t)rg * W);
+    } else {
+        rg = (uint32_t)(g / W);
+        w = (uint32_t)(g - (uint64_t)rg * W);
+    }
     const uint32_t i0 = rg * R;
     const uint32_t wl = (w == 0 ? W : w) - 1u;
     const uint32_t wr = (w + 1u == W) ? 0u : w + 1u;
@@ -447,9 +456,12 @@ __global__ __launch_bounds__(kBlock) void k_sweep_ising(Lattice lat, uint32_t c,
         __shared__ IsingQueue<R> Q;
         for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
             ising_tile<MEASURE, R>(lat, c, t, gt, tile, Q, e);
+    } else if (lat.W % kBlock == 0) {
+        for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+            ising_tile_lazy<MEASURE, R, true>(lat, c, t, gt, tile, e);
     } else {
         for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-            ising_tile_lazy<MEASURE, R>(lat, c, t, gt, tile, e);
+            ising_tile_lazy<MEASURE, R, false>(lat, c, t, gt, tile, e);
     }
     if (MEASURE)
         block_reduce_atomic<kEmCounters>(e, acc);
@@ -494,8 +506,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica 
         if (rep.lat.model == kIsing) {
             if constexpr (variant_queue(V))
                 ising_tile<false, R>(rep.lat, c, t, gt, local, Q, e);
+            else if (rep.lat.W % kBlock == 0)
+                ising_tile_lazy<false, R, true>(rep.lat, c, t, gt, local, e);
             else
-                ising_tile_lazy<false, R>(rep.lat, c, t, gt, local, e);
+                ising_tile_lazy<false, R, false>(rep.lat, c, t, gt, local, e);
         } else if (rep.lat.bc_groups == kBcGroupsDelta0)
             bc_tile<false, R, kBcGroupsDelta0>(rep.lat, c, t, gt, local, e);
         else
