@@ -160,8 +160,9 @@ int spin_threshold_table(int model, double J, double Delta, double T, uint32_t *
 
 /* Sweep strategy of a handle (results never depend on it; speed does):
  *   0: 8 rows per thread, each thread finishes its words' random planes
- *   1: 4 rows per thread, undecided Ising words go through a block queue
- *   2: 8 rows per thread, block queue      3: 4 rows per thread, per word
+ *   1: 4 rows per thread; Ising words still undecided after 8 planes go
+ *      to a per-wavefront work list that the wavefront drains together
+ *   2: 8 rows per thread, work list        3: 4 rows per thread, per word
  * spin_set_variant sets one (-EINVAL outside 0..3); spin_tune times every
  * strategy on a scratch lattice of the handle's model and size (capped at
  * L = 16384) at bath temperature T and keeps the fastest. */

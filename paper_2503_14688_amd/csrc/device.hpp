@@ -118,26 +118,6 @@ __device__ __forceinline__ uint32_t metropolis_accept(const uint32_t (&need)[NG]
     return accepted;
 }
 
-// Append slot to an LDS queue for every lane where pred holds: one LDS atomic
-// per wavefront, positions from the lane's rank among the set ballot bits.
-__device__ __forceinline__ void wave_enqueue(bool pred, uint32_t slot, uint16_t *queue, int *count)
-{
-    const unsigned long long mask = __ballot(pred);
-    if (mask == 0)
-        return;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll(mask) - 1;
-    int base = 0;
-    if (lane == leader)
-        base = atomicAdd(count, __popcll(mask));
-    base = __shfl(base, leader, 64);
-    if (pred) {
-        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-        queue[base + (int)rank] = (uint16_t)slot;
-    }
-}
-
 // Full adder and half adder on bit-sliced operands.
 __device__ __forceinline__ void full_add(uint32_t a, uint32_t b, uint32_t c, uint32_t &s, uint32_t &carry)
 {

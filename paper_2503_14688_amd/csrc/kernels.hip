@@ -8,6 +8,8 @@
 // the same (w, b) in rows i -+ 1 of the other plane; its horizontal
 // neighbours are (i, m) and (i, m - 1) of the other plane when (i + c) is
 // even, (i, m) and (i, m + 1) when it is odd.
+#include <type_traits>
+
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -111,22 +113,30 @@ __global__ __launch_bounds__(kBlock) void k_init_bc(uint32_t *planes, uint32_t L
 // tiles of one lattice; the batched kernel walks a flat list of the tiles of
 // many lattices.
 
-// Ising half-sweep with a block-wide work queue for the random planes.
-// Phase 1: every word gets its classes and the first Philox block (planes
-// 0-3), which settles most sites.  Words with sites still undecided go to an
-// LDS queue; each later round hands one queued word per thread the next
-// block, so a Philox call is spent only where a site still needs a plane (a
-// per-word loop makes the whole wavefront wait for its slowest word).  Phase
-// 3 writes the words back.  Every site ends with the outcome that all 32
-// planes define.
-template <int R>
-struct IsingQueue {
-    static constexpr int kSlots = R * kBlock;
-    uint32_t U[kSlots], A[kSlots], m3[kSlots], m4[kSlots];
-    uint16_t q[2][kSlots];
-    uint32_t i0[kBlock], w[kBlock];
-    int count[2];
+// Ising half-sweep, compacting form.  Every word gets its classes and the
+// first two Philox blocks (planes 0-7) in place, which settles all sites of
+// about nine words in ten.  The rest go to a work list owned by the
+// wavefront (ballot ranks, no block barrier); the wavefront then drains the
+// list with one word per lane, so the later blocks are drawn for the few
+// words that need them and not for every word of a wavefront that holds one
+// slow word.  Every site ends with the outcome that all 32 planes define.
+constexpr int kWaves = kBlock / 64;
+constexpr int kListCap = 128;  // list slots per wavefront; later words finish in place
+
+struct WaveList {
+    uint32_t und[kWaves][kListCap], acc[kWaves][kListCap];
+    uint32_t m3[kWaves][kListCap], m4[kWaves][kListCap];
+    uint16_t slot[kWaves][kListCap];  // row offset << 6 | owning lane
+    uint32_t i0[kWaves][64], w[kWaves][64];
 };
+
+// Orders the LDS accesses of one wavefront's lanes (no cross-wave effect).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 struct IsingNbrs {
     uint32_t up, dn, cur, side;
@@ -146,9 +156,9 @@ __device__ __forceinline__ IsingNbrs ising_nbrs(const uint32_t *oth, uint32_t L,
     return n;
 }
 
-template <bool MEASURE, int R>
-__device__ __forceinline__ void ising_tile(const Lattice &lat, uint32_t c, uint32_t t, const GroupTable &gt,
-                                           uint64_t tile, IsingQueue<R> &Q, unsigned long long (&e)[kEmCounters])
+template <bool MEASURE, int R, bool UNIFORM>
+__device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t c, uint32_t t, const GroupTable &gt,
+                                                   uint64_t tile, WaveList &Q, unsigned long long (&e)[kEmCounters])
 {
     const uint32_t L = lat.L, W = lat.W;
     uint32_t *own = lat.planes + (c ? lat.plane_u32 : 0);
@@ -158,90 +168,106 @@ __device__ __forceinline__ void ising_tile(const Lattice &lat, uint32_t c, uint3
     const bool rng3 = gt.rng_bits & 1u, rng4 = gt.rng_bits & 2u;
     const bool nev3 = gt.never_bits & 1u, nev4 = gt.never_bits & 2u;
     const uint32_t k0 = lat.key0, k1 = lat.key1;
-    const uint32_t tid = threadIdx.x;
-    const uint64_t g = tile * kBlock + tid;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint64_t g = tile * kBlock + threadIdx.x;
     const bool valid = g < nitems;
-    const uint32_t rg = valid ? (uint32_t)(g / W) : 0u;
-    const uint32_t w = valid ? (uint32_t)(g - (uint64_t)rg * W) : 0u;
+    uint32_t rg, w;
+    if (UNIFORM) {
+        rg = __builtin_amdgcn_readfirstlane((uint32_t)((tile * kBlock) / W));
+        w = (uint32_t)(g - (uint64_t)rg * W);
+    } else {
+        rg = valid ? (uint32_t)(g / W) : 0u;
+        w = valid ? (uint32_t)(g - (uint64_t)rg * W) : 0u;
+    }
     const uint32_t i0 = rg * R;
-    Q.i0[tid] = i0;
-    Q.w[tid] = w;
-    if (tid == 0)
-        Q.count[0] = 0;
-    __syncthreads();
-    uint32_t s[R], A[R];
-    uint32_t queued = 0;
+    Q.i0[wave][lane] = i0;
+    Q.w[wave][lane] = w;
+    uint32_t s[R], A[R], pos[R];
+    uint32_t queued = 0, n = 0;
+    const uint32_t wl = (w == 0 ? W : w) - 1u;
+    const uint32_t wr = (w + 1u == W) ? 0u : w + 1u;
+    uint32_t up = 0, cur = 0;
     if (valid) {
-        const uint32_t wl = (w == 0 ? W : w) - 1u;
-        const uint32_t wr = (w + 1u == W) ? 0u : w + 1u;
-        uint32_t up = oth[(size_t)(i0 == 0 ? L - 1 : i0 - 1) * W + w];
-        uint32_t cur = oth[(size_t)i0 * W + w];
+        up = oth[(size_t)(i0 == 0 ? L - 1 : i0 - 1) * W + w];
+        cur = oth[(size_t)i0 * W + w];
+    }
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t i = i0 + (uint32_t)r;
+    for (int r = 0; r < R; ++r) {
+        const uint32_t i = i0 + (uint32_t)r;
+        uint32_t sv = 0, acc = 0, und = 0, need[2] = {0u, 0u}, dn = 0;
+        if (valid) {
             const uint32_t inext = (i + 1u == L) ? 0u : i + 1u;
-            const uint32_t dn = oth[(size_t)inext * W + w];
+            dn = oth[(size_t)inext * W + w];
             const uint32_t odd = (i + c) & 1u;
             const uint32_t side = side_word(cur, oth[(size_t)i * W + (odd ? wr : wl)], odd);
-            const uint32_t sv = own[(size_t)i * W + w];
+            sv = own[(size_t)i * W + w];
             // aligned-neighbour indicators; a = number aligned, dE = J (4a - 8)
             const uint32_t e1 = ~(sv ^ up), e2 = ~(sv ^ dn), e3 = ~(sv ^ cur), e4 = ~(sv ^ side);
             const uint32_t a1 = e1 & e2, x1 = e1 ^ e2, a2 = e3 & e4, x2 = e3 ^ e4;
             const uint32_t m4 = a1 & a2;                // a = 4: dE = 8J
             const uint32_t m3 = (a1 & x2) | (a2 & x1);  // a = 3: dE = 4J
-            const uint32_t need[2] = {rng3 ? m3 : 0u, rng4 ? m4 : 0u};
+            need[0] = rng3 ? m3 : 0u;
+            need[1] = rng4 ? m4 : 0u;
             const uint32_t never = (nev3 ? m3 : 0u) | (nev4 ? m4 : 0u);
-            uint32_t acc_mask = ~(need[0] | need[1] | never);
-            uint32_t und = need[0] | need[1];
+            acc = ~(need[0] | need[1] | never);
+            und = need[0] | need[1];
             if (und != 0u) {
                 const Block4 b = philox4x32_10(i, w, t, stream_tag(kPurposeAccept, c, 0), k0, k1);
-                apply_block<2>(b, 0u, need, thr, und, acc_mask);
+                apply_block<2>(b, 0u, need, thr, und, acc);
             }
-            s[r] = sv;
-            A[r] = acc_mask;
-            const uint32_t slot = (uint32_t)r * kBlock + tid;
             if (und != 0u) {
-                Q.U[slot] = und;
-                Q.A[slot] = acc_mask;
-                Q.m3[slot] = need[0];
-                Q.m4[slot] = need[1];
-                queued |= 1u << r;
+                const Block4 b = philox4x32_10(i, w, t, stream_tag(kPurposeAccept, c, 1), k0, k1);
+                apply_block<2>(b, 1u, need, thr, und, acc);
             }
-            wave_enqueue(und != 0u, slot, Q.q[0], &Q.count[0]);
-            up = cur;
-            cur = dn;
         }
-    }
-    __syncthreads();
-    int cq = 0;
-    for (uint32_t blk = 1; blk < 8u; ++blk) {
-        const int n = Q.count[cq];
-        if (n == 0)
-            break;
-        if (tid == 0)
-            Q.count[cq ^ 1] = 0;
-        __syncthreads();
-        for (int k = (int)tid; k < n; k += kBlock) {
-            const uint32_t slot = Q.q[cq][k];
-            const uint32_t owner = slot % kBlock;
-            const uint32_t i = Q.i0[owner] + slot / kBlock;
-            const uint32_t need[2] = {Q.m3[slot], Q.m4[slot]};
-            uint32_t und = Q.U[slot], acc_mask = Q.A[slot];
-            const Block4 b = philox4x32_10(i, Q.w[owner], t, stream_tag(kPurposeAccept, c, blk), k0, k1);
-            apply_block<2>(b, blk, need, thr, und, acc_mask);
-            Q.U[slot] = und;
-            Q.A[slot] = acc_mask;
-            wave_enqueue(und != 0u, slot, Q.q[cq ^ 1], &Q.count[cq ^ 1]);
+        s[r] = sv;
+        A[r] = acc;
+        pos[r] = 0;
+        const unsigned long long bal = __ballot(und != 0u);
+        if (und != 0u) {
+            const uint32_t p = n + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            if (p < (uint32_t)kListCap) {
+                Q.und[wave][p] = und;
+                Q.acc[wave][p] = acc;
+                Q.m3[wave][p] = need[0];
+                Q.m4[wave][p] = need[1];
+                Q.slot[wave][p] = (uint16_t)(((uint32_t)r << 6) | lane);
+                pos[r] = p;
+                queued |= 1u << r;
+            } else {
+                for (uint32_t blk = 2; blk < 8u && und != 0u; ++blk) {
+                    const Block4 b = philox4x32_10(i, w, t, stream_tag(kPurposeAccept, c, blk), k0, k1);
+                    apply_block<2>(b, blk, need, thr, und, acc);
+                }
+                A[r] = acc;
+            }
         }
-        __syncthreads();
-        cq ^= 1;
+        n += (uint32_t)__popcll(bal);
+        up = cur;
+        cur = dn;
     }
+    if (n > (uint32_t)kListCap)
+        n = kListCap;
+    wave_sync();
+    for (uint32_t k = lane; k < n; k += 64u) {
+        const uint32_t slot = Q.slot[wave][k], owner = slot & 63u;
+        const uint32_t i = Q.i0[wave][owner] + (slot >> 6), wq = Q.w[wave][owner];
+        const uint32_t need[2] = {Q.m3[wave][k], Q.m4[wave][k]};
+        uint32_t und = Q.und[wave][k], acc = Q.acc[wave][k];
+        for (uint32_t blk = 2; blk < 8u && und != 0u; ++blk) {
+            const Block4 b = philox4x32_10(i, wq, t, stream_tag(kPurposeAccept, c, blk), k0, k1);
+            apply_block<2>(b, blk, need, thr, und, acc);
+        }
+        Q.acc[wave][k] = acc;
+    }
+    wave_sync();
     if (valid) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t i = i0 + (uint32_t)r;
             // sites still tied after 32 planes have u == thr: rejected
-            const uint32_t flip = ((queued >> r) & 1u) ? Q.A[(uint32_t)r * kBlock + tid] : A[r];
+            const uint32_t flip = ((queued >> r) & 1u) ? Q.acc[wave][pos[r]] : A[r];
             const uint32_t ns = s[r] ^ flip;
             own[(size_t)i * W + w] = ns;
             if (MEASURE) {
@@ -253,11 +279,11 @@ __device__ __forceinline__ void ising_tile(const Lattice &lat, uint32_t c, uint3
             }
         }
     }
-    __syncthreads();
+    wave_sync();  // the list is refilled by the next tile
 }
 
 // Ising half-sweep of one tile, one word at a time: each thread runs the
-// lazy Metropolis test of its word to completion (no queue, no LDS).
+// lazy Metropolis test of its word to completion (no list, no LDS).
 // UNIFORM: W is a multiple of kBlock, so the block's 256 items share one row
 // group; the row index is then wave-uniform and the counter words that
 // depend only on it and on t start the Philox rounds in scalar registers.
@@ -452,10 +478,15 @@ __global__ __launch_bounds__(kBlock) void k_sweep_ising(Lattice lat, uint32_t c,
     constexpr int R = variant_rows(V);
     unsigned long long e[kEmCounters] = {0, 0, 0, 0};
     const uint64_t ntiles = tiles_of<R>(lat);
-    if constexpr (variant_queue(V)) {
-        __shared__ IsingQueue<R> Q;
-        for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-            ising_tile<MEASURE, R>(lat, c, t, gt, tile, Q, e);
+    if constexpr (variant_compact(V)) {
+        __shared__ WaveList Q;
+        if (lat.W % kBlock == 0) {
+            for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+                ising_tile_compact<MEASURE, R, true>(lat, c, t, gt, tile, Q, e);
+        } else {
+            for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+                ising_tile_compact<MEASURE, R, false>(lat, c, t, gt, tile, Q, e);
+        }
     } else if (lat.W % kBlock == 0) {
         for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
             ising_tile_lazy<MEASURE, R, true>(lat, c, t, gt, tile, e);
@@ -495,7 +526,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica 
                                                              uint32_t stride, uint32_t step, uint32_t c)
 {
     constexpr int R = variant_rows(V);
-    __shared__ IsingQueue<variant_queue(V) ? R : 1> Q;
+    __shared__ std::conditional_t<variant_compact(V), WaveList, int> Q;
     unsigned long long e[kEmCounters] = {0, 0, 0, 0};
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const uint32_t rid = tile_rep[tile];
@@ -504,9 +535,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica 
         const uint64_t local = tile - rep.tile0;
         const uint32_t t = rep.t0 + step;
         if (rep.lat.model == kIsing) {
-            if constexpr (variant_queue(V))
-                ising_tile<false, R>(rep.lat, c, t, gt, local, Q, e);
-            else if (rep.lat.W % kBlock == 0)
+            if constexpr (variant_compact(V)) {
+                if (rep.lat.W % kBlock == 0)
+                    ising_tile_compact<false, R, true>(rep.lat, c, t, gt, local, Q, e);
+                else
+                    ising_tile_compact<false, R, false>(rep.lat, c, t, gt, local, Q, e);
+            } else if (rep.lat.W % kBlock == 0)
                 ising_tile_lazy<false, R, true>(rep.lat, c, t, gt, local, e);
             else
                 ising_tile_lazy<false, R, false>(rep.lat, c, t, gt, local, e);
@@ -703,12 +737,10 @@ hipError_t launch_half_sweep_v(const Lattice &lat, uint32_t colour, uint32_t t, 
     constexpr int R = variant_rows(V);
     const uint64_t tiles = tiles_of<R>(lat);
     const dim3 block(kBlock);
-    // per-word strategies: many more blocks than fit at once (the hardware
-    // keeps every CU full); queued strategies hold LDS state per block and use
-    // exactly the resident number of blocks
+    // many more blocks than fit at once: the hardware keeps every CU full
+    // while a block's grid-stride loop walks its tiles
     if (lat.model == kIsing) {
-        static const unsigned g =
-            variant_queue(V) ? resident_grid(k_sweep_ising<M, V>, 0, ~0ull) : 65536u;
+        static const unsigned g = 65536u;
         hipLaunchKernelGGL((k_sweep_ising<M, V>), dim3(g < tiles ? g : (unsigned)tiles), block, 0, st, lat, colour,
                            t, gt, em_acc);
     } else {

@@ -35,16 +35,17 @@ struct Lattice {
     int model;
     uint32_t key0, key1;
     uint32_t bc_groups;  // Blume-Capel acceptance groups in use: 13, or 6 when Delta = 0
-    int variant;         // sweep strategy, see variant_rows / variant_queue
+    int variant;         // sweep strategy, see variant_rows / variant_compact
 };
 
 // Sweep strategies: rows walked per thread (4 or 8) and, for Ising, whether
-// undecided words go through the block's LDS work queue (ising_tile) or each
-// thread finishes its word's lazy test itself (ising_tile_lazy).
-//   0: 8 rows, per word   1: 4 rows, queue   2: 8 rows, queue   3: 4 rows, per word
+// words still undecided after eight planes go to the wavefront's LDS work
+// list (ising_tile_compact) or each thread finishes its word's lazy test
+// itself (ising_tile_lazy).  Blume-Capel uses the row count only.
+//   0: 8 rows, per word   1: 4 rows, compacting   2: 8 rows, compacting   3: 4 rows, per word
 constexpr int kVariants = 4;
 __host__ __device__ constexpr int variant_rows(int v) { return (v == 1 || v == 3) ? 4 : 8; }
-__host__ __device__ constexpr bool variant_queue(int v) { return v == 1 || v == 2; }
+__host__ __device__ constexpr bool variant_compact(int v) { return v == 1 || v == 2; }
 
 // Counters of the energy/magnetisation reduction (both colours):
 //   acc[0] = #(s != 0)  acc[1] = #(s < 0)
