@@ -165,7 +165,10 @@ int spin_threshold_table(int model, double J, double Delta, double T, uint32_t *
  *   2: 8 rows per thread, work list        3: 4 rows per thread, per word
  * spin_set_variant sets one (-EINVAL outside 0..3); spin_tune times every
  * strategy on a scratch lattice of the handle's model and size (capped at
- * L = 16384) at bath temperature T and keeps the fastest. */
+ * L = 32768; allocated and freed by the call) at bath temperature T, after
+ * 16 warm-up sweeps from a T = infinity start, best of three interleaved
+ * rounds, and keeps the fastest.  Synchronises the handle's stream; the
+ * handle's own lattice and sweep index are untouched. */
 int spin_set_variant(spin_handle *h, int variant);
 int spin_get_variant(const spin_handle *h, int *variant);
 int spin_tune(spin_handle *h, double T, int *chosen);

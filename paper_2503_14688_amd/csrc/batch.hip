@@ -2,8 +2,9 @@
 // size and model, each following its own bath-temperature schedule (paper,
 // Thermal protocols), advanced together by one launch per half-sweep over a
 // flat list of all replicas' tiles.  A run of n sweeps is captured once as a
-// HIP graph of 2n launches and replayed; the rows-per-thread tile shape is
-// chosen by timing both shapes on scratch copies of the lattices.
+// HIP graph of 2n launches and replayed; the sweep strategy (rows per thread,
+// per-word or compacting lazy test) is chosen by timing every strategy on
+// scratch copies of the lattices.
 #include "host.hpp"
 
 #include <algorithm>
@@ -113,73 +114,97 @@ int launch_sweeps(spin_batch *b, int variant, uint64_t t0, uint32_t n, hipStream
     return 0;
 }
 
-// Choose the sweep strategy: copy every lattice to scratch memory, time two
-// sweeps of each strategy on the copies with HIP events, keep the fastest.
+// Choose the sweep strategy on scratch copies of every lattice.  The cost of
+// a sweep grows as a lattice relaxes from its T = infinity start, so the
+// copies are first warmed up with eight sweeps at the current schedule step;
+// then every strategy is timed (HIP events, two sweeps) in three interleaved
+// rounds on the same evolving copies, and the best time of each counts.
 int autotune(spin_batch *b)
 {
+    auto padded = [](size_t bytes) { return (bytes + 255) / 256 * 256; };
     size_t total = 0;
     for (spin_handle *h : b->reps)
-        total += (h->buf_bytes + 255) / 256 * 256;
+        total += padded(h->buf_bytes);
     char *scratch = nullptr;
     if (hipMalloc(&scratch, total) != hipSuccess) {
         (void)hipGetLastError();
         b->variant = 0;  // no room to tune: keep the default strategy
         return 0;
     }
-    size_t off = 0;
-    for (spin_handle *h : b->reps) {
-        HIP_TRY(hipMemcpyAsync(scratch + off, h->buf, h->buf_bytes, hipMemcpyDeviceToDevice, b->stream),
-                "hipMemcpyAsync");
-        off += (h->buf_bytes + 255) / 256 * 256;
-    }
-    // descriptor copies pointing at the scratch lattices
-    float best_ms = 0.0f;
-    int best = 0;
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
-    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
-    for (int v = 0; v < spin::kVariants; ++v) {
-        const int k = shape_of(v);
-        std::vector<spin::BatchReplica> host(b->reps.size());
-        HIP_TRY(hipMemcpy(host.data(), b->d_reps[k], host.size() * sizeof(spin::BatchReplica),
-                          hipMemcpyDeviceToHost),
-                "hipMemcpy");
-        size_t o = 0;
-        for (size_t r = 0; r < host.size(); ++r) {
-            host[r].lat.planes = (uint32_t *)(scratch + o);
-            o += (b->reps[r]->buf_bytes + 255) / 256 * 256;
+    spin::BatchReplica *keep[2] = {b->d_reps[0], b->d_reps[1]};
+    spin::BatchReplica *tmp[2] = {nullptr, nullptr};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float best_ms[spin::kVariants] = {};
+    int rc = 0;
+    hipError_t e = hipSuccess;
+    do {
+        size_t off = 0;
+        for (spin_handle *h : b->reps) {
+            if ((e = hipMemcpyAsync(scratch + off, h->buf, h->buf_bytes, hipMemcpyDeviceToDevice, b->stream)) !=
+                hipSuccess)
+                break;
+            off += padded(h->buf_bytes);
         }
-        spin::BatchReplica *d_tmp = nullptr;
-        HIP_TRY(hipMalloc(&d_tmp, host.size() * sizeof(spin::BatchReplica)), "hipMalloc");
-        HIP_TRY(hipMemcpy(d_tmp, host.data(), host.size() * sizeof(spin::BatchReplica), hipMemcpyHostToDevice),
-                "hipMemcpy");
-        spin::BatchReplica *keep = b->d_reps[k];
-        b->d_reps[k] = d_tmp;
-        // the current schedule step is the only one known to exist: time it
-        int rc = launch_sweeps(b, v, b->t, 1, b->stream);  // warm-up
-        if (!rc) {
-            HIP_TRY(hipEventRecord(e0, b->stream), "hipEventRecord");
-            rc = launch_sweeps(b, v, b->t, 1, b->stream);
-            if (!rc)
-                rc = launch_sweeps(b, v, b->t, 1, b->stream);
-            HIP_TRY(hipEventRecord(e1, b->stream), "hipEventRecord");
-            HIP_TRY(hipEventSynchronize(e1), "hipEventSynchronize");
+        // descriptor copies pointing at the scratch lattices, per tile shape
+        const size_t n = b->reps.size();
+        std::vector<spin::BatchReplica> host(n);
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+            if ((e = hipMemcpy(host.data(), keep[k], n * sizeof(spin::BatchReplica), hipMemcpyDeviceToHost)) !=
+                hipSuccess)
+                break;
+            size_t o = 0;
+            for (size_t r = 0; r < n; ++r) {
+                host[r].lat.planes = (uint32_t *)(scratch + o);
+                o += padded(b->reps[r]->buf_bytes);
+            }
+            if ((e = hipMalloc(&tmp[k], n * sizeof(spin::BatchReplica))) != hipSuccess)
+                break;
+            e = hipMemcpy(tmp[k], host.data(), n * sizeof(spin::BatchReplica), hipMemcpyHostToDevice);
         }
-        b->d_reps[k] = keep;
-        (void)hipFree(d_tmp);
-        if (rc)
-            return rc;
-        float ms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-        if (best_ms == 0.0f || ms < best_ms) {
-            best_ms = ms;
-            best = v;
+        if (e == hipSuccess && (e = hipEventCreate(&e0)) == hipSuccess)
+            e = hipEventCreate(&e1);
+        if (e != hipSuccess)
+            break;
+        b->d_reps[0] = tmp[0];
+        b->d_reps[1] = tmp[1];
+        // the current schedule step is the only one known to exist: every
+        // tuning sweep uses it
+        for (int w = 0; w < 8 && rc == 0; ++w)
+            rc = launch_sweeps(b, 0, b->t, 1, b->stream);
+        for (int round = 0; round < 3 && rc == 0 && e == hipSuccess; ++round) {
+            for (int v = 0; v < spin::kVariants && rc == 0 && e == hipSuccess; ++v) {
+                if ((e = hipEventRecord(e0, b->stream)) != hipSuccess)
+                    break;
+                rc = launch_sweeps(b, v, b->t, 2, b->stream);
+                if (rc)
+                    break;
+                float ms = 0.0f;
+                if ((e = hipEventRecord(e1, b->stream)) == hipSuccess && (e = hipEventSynchronize(e1)) == hipSuccess)
+                    e = hipEventElapsedTime(&ms, e0, e1);
+                if (e == hipSuccess && (round == 0 || ms < best_ms[v]))
+                    best_ms[v] = ms;
+            }
         }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    } while (false);
+    b->d_reps[0] = keep[0];
+    b->d_reps[1] = keep[1];
+    if (rc == 0 && e != hipSuccess)
+        rc = hip_fail(e, "batch strategy tuning");
+    (void)hipStreamSynchronize(b->stream);
+    for (int k = 0; k < 2; ++k)
+        if (tmp[k])
+            (void)hipFree(tmp[k]);
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
     (void)hipFree(scratch);
+    if (rc)
+        return rc;
+    int best = 0;
+    for (int v = 1; v < spin::kVariants; ++v)
+        if (best_ms[v] < best_ms[best])
+            best = v;
     b->variant = best;
     return 0;
 }

@@ -115,17 +115,18 @@ __global__ __launch_bounds__(kBlock) void k_init_bc(uint32_t *planes, uint32_t L
 
 // Ising half-sweep, compacting form.  Every word gets its classes and the
 // first two Philox blocks (planes 0-7) in place, which settles all sites of
-// about nine words in ten.  The rest go to a work list owned by the
-// wavefront (ballot ranks, no block barrier); the wavefront then drains the
-// list with one word per lane, so the later blocks are drawn for the few
-// words that need them and not for every word of a wavefront that holds one
-// slow word.  Every site ends with the outcome that all 32 planes define.
+// about nine words in ten; those are written back at once.  The rest go to a
+// work list owned by the wavefront (ballot ranks, no block barrier); the
+// wavefront then drains the list with one word per lane and writes those
+// words, so the later blocks are drawn for the few words that need them and
+// not for every word of a wavefront that holds one slow word.  Every site
+// ends with the outcome that all 32 planes define.
 constexpr int kWaves = kBlock / 64;
 constexpr int kListCap = 128;  // list slots per wavefront; later words finish in place
 
 struct WaveList {
     uint32_t und[kWaves][kListCap], acc[kWaves][kListCap];
-    uint32_t m3[kWaves][kListCap], m4[kWaves][kListCap];
+    uint32_t m3[kWaves][kListCap], m4[kWaves][kListCap], s[kWaves][kListCap];
     uint16_t slot[kWaves][kListCap];  // row offset << 6 | owning lane
     uint32_t i0[kWaves][64], w[kWaves][64];
 };
@@ -156,6 +157,18 @@ __device__ __forceinline__ IsingNbrs ising_nbrs(const uint32_t *oth, uint32_t L,
     return n;
 }
 
+// Energy/magnetisation counters of one updated word (see kEmCounters): the
+// word's 32 sites and the 32 other-colour sites at the same position, and
+// the four bonds of each updated site.
+__device__ __forceinline__ void ising_em(unsigned long long (&e)[kEmCounters], uint32_t ns, uint32_t up,
+                                         uint32_t dn, uint32_t cur, uint32_t side)
+{
+    e[0] += 64;
+    e[1] += __popc(ns) + __popc(cur);
+    e[2] += 128;
+    e[3] += __popc(ns ^ up) + __popc(ns ^ dn) + __popc(ns ^ cur) + __popc(ns ^ side);
+}
+
 template <bool MEASURE, int R, bool UNIFORM>
 __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t c, uint32_t t, const GroupTable &gt,
                                                    uint64_t tile, WaveList &Q, unsigned long long (&e)[kEmCounters])
@@ -182,25 +195,34 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
     const uint32_t i0 = rg * R;
     Q.i0[wave][lane] = i0;
     Q.w[wave][lane] = w;
-    uint32_t s[R], A[R], pos[R];
-    uint32_t queued = 0, n = 0;
+    uint32_t n = 0;
     const uint32_t wl = (w == 0 ? W : w) - 1u;
     const uint32_t wr = (w + 1u == W) ? 0u : w + 1u;
-    uint32_t up = 0, cur = 0;
-    if (valid) {
-        up = oth[(size_t)(i0 == 0 ? L - 1 : i0 - 1) * W + w];
-        cur = oth[(size_t)i0 * W + w];
-    }
+    // Words of row i0 and its vertical neighbours; each row below loads the
+    // next row's words before it draws random planes, so the loads are in
+    // flight while the Philox rounds run.  Lanes past the end of the lattice
+    // (rg = w = 0) load rows 0..R of column 0, which exist, and never use the
+    // values: the loads stay unconditional, so the wait before a row covers
+    // only that row's words.
+    uint32_t up = oth[(size_t)(i0 == 0 ? L - 1 : i0 - 1) * W + w];
+    uint32_t cur = oth[(size_t)i0 * W + w];
+    uint32_t dn = oth[(size_t)(i0 + 1u == L ? 0u : i0 + 1u) * W + w];
+    uint32_t nbw = oth[(size_t)i0 * W + (((i0 + c) & 1u) ? wr : wl)];
+    uint32_t sv = own[(size_t)i0 * W + w];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t i = i0 + (uint32_t)r;
-        uint32_t sv = 0, acc = 0, und = 0, need[2] = {0u, 0u}, dn = 0;
+        uint32_t dn2 = 0, nbw2 = 0, sv2 = 0;
+        if (r + 1 < R) {
+            const uint32_t i1 = i + 1u;  // i0 + R <= L: still in the tile
+            dn2 = oth[(size_t)(i1 + 1u == L ? 0u : i1 + 1u) * W + w];
+            nbw2 = oth[(size_t)i1 * W + (((i1 + c) & 1u) ? wr : wl)];
+            sv2 = own[(size_t)i1 * W + w];
+        }
+        const uint32_t odd = (i + c) & 1u;
+        const uint32_t side = side_word(cur, nbw, odd);
+        uint32_t acc = 0, und = 0, need[2] = {0u, 0u};
         if (valid) {
-            const uint32_t inext = (i + 1u == L) ? 0u : i + 1u;
-            dn = oth[(size_t)inext * W + w];
-            const uint32_t odd = (i + c) & 1u;
-            const uint32_t side = side_word(cur, oth[(size_t)i * W + (odd ? wr : wl)], odd);
-            sv = own[(size_t)i * W + w];
             // aligned-neighbour indicators; a = number aligned, dE = J (4a - 8)
             const uint32_t e1 = ~(sv ^ up), e2 = ~(sv ^ dn), e3 = ~(sv ^ cur), e4 = ~(sv ^ side);
             const uint32_t a1 = e1 & e2, x1 = e1 ^ e2, a2 = e3 & e4, x2 = e3 ^ e4;
@@ -213,17 +235,15 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
             und = need[0] | need[1];
             if (und != 0u) {
                 const Block4 b = philox4x32_10(i, w, t, stream_tag(kPurposeAccept, c, 0), k0, k1);
-                apply_block<2>(b, 0u, need, thr, und, acc);
+                apply_block_2g(b, 0u, need, thr, und, acc);
             }
             if (und != 0u) {
                 const Block4 b = philox4x32_10(i, w, t, stream_tag(kPurposeAccept, c, 1), k0, k1);
-                apply_block<2>(b, 1u, need, thr, und, acc);
+                apply_block_2g(b, 1u, need, thr, und, acc);
             }
         }
-        s[r] = sv;
-        A[r] = acc;
-        pos[r] = 0;
         const unsigned long long bal = __ballot(und != 0u);
+        bool listed = false;
         if (und != 0u) {
             const uint32_t p = n + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
@@ -232,20 +252,29 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
                 Q.acc[wave][p] = acc;
                 Q.m3[wave][p] = need[0];
                 Q.m4[wave][p] = need[1];
+                Q.s[wave][p] = sv;
                 Q.slot[wave][p] = (uint16_t)(((uint32_t)r << 6) | lane);
-                pos[r] = p;
-                queued |= 1u << r;
+                listed = true;
             } else {
                 for (uint32_t blk = 2; blk < 8u && und != 0u; ++blk) {
                     const Block4 b = philox4x32_10(i, w, t, stream_tag(kPurposeAccept, c, blk), k0, k1);
-                    apply_block<2>(b, blk, need, thr, und, acc);
+                    apply_block_2g(b, blk, need, thr, und, acc);
                 }
-                A[r] = acc;
             }
+        }
+        if (valid && !listed) {
+            // sites still tied after 32 planes have u == thr: rejected
+            const uint32_t ns = sv ^ acc;
+            own[(size_t)i * W + w] = ns;
+            if (MEASURE)
+                ising_em(e, ns, up, dn, cur, side);
         }
         n += (uint32_t)__popcll(bal);
         up = cur;
         cur = dn;
+        dn = dn2;
+        nbw = nbw2;
+        sv = sv2;
     }
     if (n > (uint32_t)kListCap)
         n = kListCap;
@@ -257,26 +286,13 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
         uint32_t und = Q.und[wave][k], acc = Q.acc[wave][k];
         for (uint32_t blk = 2; blk < 8u && und != 0u; ++blk) {
             const Block4 b = philox4x32_10(i, wq, t, stream_tag(kPurposeAccept, c, blk), k0, k1);
-            apply_block<2>(b, blk, need, thr, und, acc);
+            apply_block_2g(b, blk, need, thr, und, acc);
         }
-        Q.acc[wave][k] = acc;
-    }
-    wave_sync();
-    if (valid) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t i = i0 + (uint32_t)r;
-            // sites still tied after 32 planes have u == thr: rejected
-            const uint32_t flip = ((queued >> r) & 1u) ? Q.acc[wave][pos[r]] : A[r];
-            const uint32_t ns = s[r] ^ flip;
-            own[(size_t)i * W + w] = ns;
-            if (MEASURE) {
-                const IsingNbrs nb = ising_nbrs(oth, L, W, c, i, w);
-                e[0] += 64;
-                e[1] += __popc(ns) + __popc(nb.cur);
-                e[2] += 128;
-                e[3] += __popc(ns ^ nb.up) + __popc(ns ^ nb.dn) + __popc(ns ^ nb.cur) + __popc(ns ^ nb.side);
-            }
+        const uint32_t ns = Q.s[wave][k] ^ acc;
+        own[(size_t)i * W + wq] = ns;
+        if (MEASURE) {
+            const IsingNbrs nb = ising_nbrs(oth, L, W, c, i, wq);
+            ising_em(e, ns, nb.up, nb.dn, nb.cur, nb.side);
         }
     }
     wave_sync();  // the list is refilled by the next tile
@@ -312,17 +328,26 @@ __device__ __forceinline__ void ising_tile_lazy(const Lattice &lat, uint32_t c, 
     const uint32_t i0 = rg * R;
     const uint32_t wl = (w == 0 ? W : w) - 1u;
     const uint32_t wr = (w + 1u == W) ? 0u : w + 1u;
+    // row i0's words; each row loads the next row's words before its random
+    // planes are drawn
     uint32_t up = oth[(size_t)(i0 == 0 ? L - 1 : i0 - 1) * W + w];
     uint32_t cur = oth[(size_t)i0 * W + w];
+    uint32_t dn = oth[(size_t)(i0 + 1u == L ? 0u : i0 + 1u) * W + w];
+    uint32_t nbw = oth[(size_t)i0 * W + (((i0 + c) & 1u) ? wr : wl)];
+    uint32_t sv = own[(size_t)i0 * W + w];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t i = i0 + (uint32_t)r;
-        const uint32_t inext = (i + 1u == L) ? 0u : i + 1u;
-        const uint32_t dn = oth[(size_t)inext * W + w];
+        uint32_t dn2 = 0, nbw2 = 0, sv2 = 0;
+        if (r + 1 < R) {
+            const uint32_t i1 = i + 1u;  // i0 + R <= L: still in the tile
+            dn2 = oth[(size_t)(i1 + 1u == L ? 0u : i1 + 1u) * W + w];
+            nbw2 = oth[(size_t)i1 * W + (((i1 + c) & 1u) ? wr : wl)];
+            sv2 = own[(size_t)i1 * W + w];
+        }
         const uint32_t odd = (i + c) & 1u;
-        const uint32_t side = side_word(cur, oth[(size_t)i * W + (odd ? wr : wl)], odd);
+        const uint32_t side = side_word(cur, nbw, odd);
         const size_t idx = (size_t)i * W + w;
-        const uint32_t sv = own[idx];
         // aligned-neighbour indicators; a = number aligned, dE = J (4a - 8)
         const uint32_t e1 = ~(sv ^ up), e2 = ~(sv ^ dn), e3 = ~(sv ^ cur), e4 = ~(sv ^ side);
         const uint32_t a1 = e1 & e2, x1 = e1 ^ e2, a2 = e3 & e4, x2 = e3 ^ e4;
@@ -334,14 +359,13 @@ __device__ __forceinline__ void ising_tile_lazy(const Lattice &lat, uint32_t c, 
         const uint32_t flip = metropolis_accept<2>(need, thr, always, i, w, t, c, lat.key0, lat.key1);
         const uint32_t ns = sv ^ flip;
         own[idx] = ns;
-        if (MEASURE) {
-            e[0] += 64;
-            e[1] += __popc(ns) + __popc(cur);
-            e[2] += 128;
-            e[3] += __popc(ns ^ up) + __popc(ns ^ dn) + __popc(ns ^ cur) + __popc(ns ^ side);
-        }
+        if (MEASURE)
+            ising_em(e, ns, up, dn, cur, side);
         up = cur;
         cur = dn;
+        dn = dn2;
+        nbw = nbw2;
+        sv = sv2;
     }
 }
 
