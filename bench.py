@@ -48,7 +48,7 @@ def cpu_baseline(workload, budget_s=12.0):
     threads = oracle.num_threads()
     done = 0
     t0 = time.perf_counter()
-    while done < 64:
+    while done < 4096:
         oracle.sweep(model, s, workload["seed"], workload.get("J", 1.0), workload.get("Delta", 0.0), done,
                      np.array([T]))
         done += 1

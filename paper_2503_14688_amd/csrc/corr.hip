@@ -7,12 +7,14 @@
 // shift of the partner plane (r even: same colour, m + r/2; r odd: other
 // colour, m + (r-1)/2 + ((i + c) & 1)), so with the set known at compile time
 // each pair costs one funnel shift, one XOR and one accumulating popcount.
+// The two halves of a block take 24 separations each.
 //
 // Vertical (k_corr_y_ring): a block owns a 4-word (Ising) or 2-word
 // (Blume-Capel) column strip of both planes and walks down the lattice once,
 // keeping the last r_max + 256 rows in an LDS ring; each new row meets its
-// 48 partners above it in the ring, so the lattice is read from HBM about
-// once for all separations.
+// 48 partners above it in the ring (four threads per row, twelve
+// separations each), so the lattice is read from HBM about once for all
+// separations.
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -50,14 +52,21 @@ struct XTile {
     uint32_t w[2][(kTileW + kHalo) * E];
 };
 
-// Pairs of one own word (plane C, row parity P) with all requested r.
-// Every separation of the set is computed (no per-r branch, so the LDS
-// reads pipeline); counters past the requested prefix are dropped at the end.
-template <int MODEL, int C, int P, int Q>
+// Separation groups: each half of a block pairs the words of the staged
+// segment with 24 of the 48 separations (counters for 24 only, so the kernel
+// keeps fewer registers per lane and more wavefronts per CU).
+constexpr int kXGroups = 2;
+constexpr int kXPer = kSparseN / kXGroups;
+
+// Pairs of one own word (plane C, row parity P) with separations Q0 .. Q0 +
+// kXPer - 1.  Every separation of the group is computed (no per-r branch, so
+// the LDS reads pipeline); counters past the requested prefix are dropped at
+// the end.
+template <int MODEL, int C, int P, int Q0, int Q>
 __device__ __forceinline__ void x_pairs(const XTile<MODEL> &t, int k, uint32_t oz, uint32_t os,
-                                        uint32_t (&ca)[kSparseN], uint32_t (&cb)[kSparseN])
+                                        uint32_t (&ca)[kXPer], uint32_t (&cb)[kXPer])
 {
-    if constexpr (Q < kSparseN) {
+    if constexpr (Q < Q0 + kXPer) {
         {
             constexpr uint32_t r = sparse_r(Q);
             constexpr int tc = C ^ (int)(r & 1u);
@@ -68,57 +77,88 @@ __device__ __forceinline__ void x_pairs(const XTile<MODEL> &t, int k, uint32_t o
             if constexpr (MODEL == kIsing) {
                 const uint32_t x = t.w[tc][k + qw], y = t.w[tc][k + qw + 1];
                 const uint32_t b = rr ? __builtin_amdgcn_alignbit(y, x, rr) : x;
-                cb[Q] += __popc(os ^ b);
+                cb[Q - Q0] += __popc(os ^ b);
             } else {
                 const uint32_t xz = t.w[tc][(k + qw) * E], yz = t.w[tc][(k + qw + 1) * E];
                 const uint32_t xs = t.w[tc][(k + qw) * E + 1], ys = t.w[tc][(k + qw + 1) * E + 1];
                 const uint32_t bz = rr ? __builtin_amdgcn_alignbit(yz, xz, rr) : xz;
                 const uint32_t bs = rr ? __builtin_amdgcn_alignbit(ys, xs, rr) : xs;
                 const uint32_t both = oz & bz;
-                ca[Q] += __popc(both);
-                cb[Q] += __popc(both & (os ^ bs));
+                ca[Q - Q0] += __popc(both);
+                cb[Q - Q0] += __popc(both & (os ^ bs));
             }
         }
-        x_pairs<MODEL, C, P, Q + 1>(t, k, oz, os, ca, cb);
+        x_pairs<MODEL, C, P, Q0, Q + 1>(t, k, oz, os, ca, cb);
     }
 }
 
-template <int MODEL, int C>
-__device__ __forceinline__ void x_word(const XTile<MODEL> &t, int k, uint32_t parity,
-                                       uint32_t (&ca)[kSparseN], uint32_t (&cb)[kSparseN])
+// Every word of the staged segment against the group's separations; P0 is
+// the row parity of colour 0 (colour 1 has the other).
+template <int MODEL, int P0, int Q0>
+__device__ __forceinline__ void x_segment(const XTile<MODEL> &t, int tw, uint32_t (&ca)[kXPer],
+                                          uint32_t (&cb)[kXPer])
 {
     constexpr int E = XTile<MODEL>::E;
-    const uint32_t oz = MODEL == kIsing ? ~0u : t.w[C][k * E];
-    const uint32_t os = t.w[C][k * E + (E - 1)];
-    if (parity)
-        x_pairs<MODEL, C, 1, 0>(t, k, oz, os, ca, cb);
-    else
-        x_pairs<MODEL, C, 0, 0>(t, k, oz, os, ca, cb);
+#pragma unroll 1
+    for (int k = (int)(threadIdx.x % (kBlock / kXGroups)); k < tw; k += kBlock / kXGroups) {
+#pragma unroll
+        for (int C = 0; C < 2; ++C) {
+            const uint32_t oz = MODEL == kIsing ? ~0u : t.w[C][k * E];
+            const uint32_t os = t.w[C][k * E + (E - 1)];
+            if (C == 0)
+                x_pairs<MODEL, 0, P0, Q0, Q0>(t, k, oz, os, ca, cb);
+            else
+                x_pairs<MODEL, 1, P0 ^ 1, Q0, Q0>(t, k, oz, os, ca, cb);
+        }
+    }
 }
 
-template <int N>
-__device__ __forceinline__ void flush_counts(const uint32_t (&cnt)[N], int n_r, unsigned long long *dst,
-                                             int stride)
+template <int MODEL, int P0>
+__device__ __forceinline__ void x_group(int sg, const XTile<MODEL> &t, int tw, uint32_t (&ca)[kXPer],
+                                        uint32_t (&cb)[kXPer])
 {
-    // block sum of each counter, one atomic per counter and block
-    __shared__ unsigned long long part[N];
-    for (int q = threadIdx.x; q < N; q += blockDim.x)
-        part[q] = 0;
+    static_assert(kXGroups == 2, "one branch per group");
+    if (sg == 0)  // wave-uniform
+        x_segment<MODEL, P0, 0>(t, tw, ca, cb);
+    else
+        x_segment<MODEL, P0, kXPer>(t, tw, ca, cb);
+}
+
+// Block sums of per-group counters: each wavefront adds its group's counters
+// (one LDS atomic per counter and wavefront), then one atomic per counter and
+// block to HBM.  acc[2q] takes ca, acc[2q + 1] takes cb.
+template <bool WITH_A, int PER>
+__device__ __forceinline__ void flush_groups(const uint32_t (&ca)[PER], const uint32_t (&cb)[PER], int sg,
+                                             int n_r, unsigned long long *acc)
+{
+    __shared__ unsigned long long part[2][kSparseN];
+    __syncthreads();
+    for (int q = threadIdx.x; q < 2 * kSparseN; q += blockDim.x)
+        part[q / kSparseN][q % kSparseN] = 0;
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < N; ++q) {
-        unsigned long long x = cnt[q];
+    for (int q = 0; q < PER; ++q) {
+        unsigned long long a = ca[q], b = cb[q];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-            x += __shfl_xor(x, off, 64);
-        if ((threadIdx.x & 63) == 0 && q < n_r)
-            atomicAdd(&part[q], x);
+        for (int off = 32; off > 0; off >>= 1) {
+            if (WITH_A)
+                a += __shfl_xor(a, off, 64);
+            b += __shfl_xor(b, off, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            if (WITH_A)
+                atomicAdd(&part[0][sg * PER + q], a);
+            atomicAdd(&part[1][sg * PER + q], b);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // one counter at a time: few live registers
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < n_r && q < N; q += blockDim.x)
-        if (part[q])
-            atomicAdd(dst + (size_t)q * stride, part[q]);
-    __syncthreads();
+    for (int q = threadIdx.x; q < n_r; q += blockDim.x) {
+        if (WITH_A && part[0][q])
+            atomicAdd(acc + 2 * q, part[0][q]);
+        if (part[1][q])
+            atomicAdd(acc + 2 * q + 1, part[1][q]);
+    }
 }
 
 template <int MODEL>
@@ -129,9 +169,10 @@ __global__ __launch_bounds__(kBlock) void k_corr_x_sparse(Lattice lat, int n_r, 
     const uint32_t L = lat.L, W = lat.W;
     const uint32_t tiles_per_row = (W + kTileW - 1) / kTileW;
     const uint64_t ntiles = (uint64_t)L * tiles_per_row;
-    uint32_t ca[kSparseN], cb[kSparseN];
+    const int sg = (int)(threadIdx.x / (kBlock / kXGroups));  // separation group (wave-uniform)
+    uint32_t ca[kXPer], cb[kXPer];
 #pragma unroll
-    for (int q = 0; q < kSparseN; ++q) {
+    for (int q = 0; q < kXPer; ++q) {
         ca[q] = 0;
         cb[q] = 0;
     }
@@ -150,15 +191,12 @@ __global__ __launch_bounds__(kBlock) void k_corr_x_sparse(Lattice lat, int n_r, 
             t.w[1][k] = lat.planes[lat.plane_u32 + off];
         }
         __syncthreads();
-        const uint32_t p0 = i & 1u;  // row parity of colour 0; colour 1 has the other
-        for (int k = threadIdx.x; k < tw; k += kBlock) {
-            x_word<MODEL, 0>(t, k, p0, ca, cb);
-            x_word<MODEL, 1>(t, k, p0 ^ 1u, ca, cb);
-        }
+        if (i & 1u)
+            x_group<MODEL, 1>(sg, t, tw, ca, cb);
+        else
+            x_group<MODEL, 0>(sg, t, tw, ca, cb);
     }
-    if (MODEL != kIsing)
-        flush_counts<kSparseN>(ca, n_r, acc, 2);
-    flush_counts<kSparseN>(cb, n_r, acc + 1, 2);
+    flush_groups<MODEL != kIsing, kXPer>(ca, cb, sg, n_r, acc);
 }
 
 // -------------------------------------------------------------- vertical --
@@ -190,14 +228,22 @@ __device__ __forceinline__ Row8 lds_row(const uint32_t *ring, uint32_t slot)
     return r;
 }
 
-// Pairs of the thread's partner row x (row j) with the base row j - r for
-// every r of the set.  Base plane c, partner plane c ^ (r & 1), same words.
-template <int MODEL, bool ALL_VALID, int Q>
+// Separation groups of the vertical kernel: a block has kYGroups threads per
+// ring row, each pairing the row with kYPer of the 48 separations, so four
+// times as many wavefronts share one LDS ring (the ring, not the thread
+// count, limits a CU to one block).
+constexpr int kYGroups = 4;
+constexpr int kYPer = kSparseN / kYGroups;
+constexpr int kYThreads = kChunk * kYGroups;
+
+// Pairs of the thread's partner row x (row j) with the base row j - r for the
+// separations Q0 .. Q0 + kYPer - 1.  Base plane c, partner plane c ^ (r & 1),
+// same words.
+template <int MODEL, bool ALL_VALID, int Q0, int Q>
 __device__ __forceinline__ void y_pairs(const uint32_t *ring, uint32_t slot0, int jr, const Row8 &x, int64_t j,
-                                        uint32_t L, uint32_t RING, uint32_t (&ca)[kSparseN],
-                                        uint32_t (&cb)[kSparseN])
+                                        uint32_t L, uint32_t RING, uint32_t (&ca)[kYPer], uint32_t (&cb)[kYPer])
 {
-    if constexpr (Q < kSparseN) {
+    if constexpr (Q < Q0 + kYPer) {
         {
             constexpr uint32_t r = sparse_r(Q);
             constexpr int flip = (r & 1u) ? 4 : 0;  // partner column of base column k: k ^ flip
@@ -212,7 +258,7 @@ __device__ __forceinline__ void y_pairs(const uint32_t *ring, uint32_t slot0, in
 #pragma unroll
                 for (int k = 0; k < 8; ++k)
                     n += __popc(b.v[k] ^ x.v[k ^ flip]);
-                cb[Q] += ok ? n : 0u;
+                cb[Q - Q0] += ok ? n : 0u;
             } else {
                 uint32_t na = 0, nb = 0;
 #pragma unroll
@@ -221,17 +267,35 @@ __device__ __forceinline__ void y_pairs(const uint32_t *ring, uint32_t slot0, in
                     na += __popc(both);
                     nb += __popc(both & (b.v[k + 1] ^ x.v[(k ^ flip) + 1]));
                 }
-                ca[Q] += ok ? na : 0u;
-                cb[Q] += ok ? nb : 0u;
+                ca[Q - Q0] += ok ? na : 0u;
+                cb[Q - Q0] += ok ? nb : 0u;
             }
         }
-        y_pairs<MODEL, ALL_VALID, Q + 1>(ring, slot0, jr, x, j, L, RING, ca, cb);
+        // keep at most three pairs' LDS rows in flight: the block's 16
+        // wavefronts leave each lane 128 registers
+        if constexpr ((Q - Q0) % 3 == 2)
+            __builtin_amdgcn_sched_barrier(0);
+        y_pairs<MODEL, ALL_VALID, Q0, Q + 1>(ring, slot0, jr, x, j, L, RING, ca, cb);
+    }
+}
+
+template <int MODEL, bool ALL_VALID>
+__device__ __forceinline__ void y_group(int sg, const uint32_t *ring, uint32_t slot0, int jr, const Row8 &x,
+                                        int64_t j, uint32_t L, uint32_t RING, uint32_t (&ca)[kYPer],
+                                        uint32_t (&cb)[kYPer])
+{
+    static_assert(kYGroups == 4, "one case per group");
+    switch (sg) {  // wave-uniform
+    case 0: y_pairs<MODEL, ALL_VALID, 0, 0>(ring, slot0, jr, x, j, L, RING, ca, cb); break;
+    case 1: y_pairs<MODEL, ALL_VALID, kYPer, kYPer>(ring, slot0, jr, x, j, L, RING, ca, cb); break;
+    case 2: y_pairs<MODEL, ALL_VALID, 2 * kYPer, 2 * kYPer>(ring, slot0, jr, x, j, L, RING, ca, cb); break;
+    default: y_pairs<MODEL, ALL_VALID, 3 * kYPer, 3 * kYPer>(ring, slot0, jr, x, j, L, RING, ca, cb); break;
     }
 }
 
 template <int MODEL>
-__global__ __launch_bounds__(kBlock) void k_corr_y_ring(Lattice lat, int n_r, uint32_t RING,
-                                                        unsigned long long *acc)
+__global__ __launch_bounds__(kYThreads) void k_corr_y_ring(Lattice lat, int n_r, uint32_t RING,
+                                                           unsigned long long *acc)
 {
     extern __shared__ uint32_t ring[];  // (RING + kChunk) rows of kRingCols words
     constexpr int SW = YShape<MODEL>::SW;
@@ -241,15 +305,30 @@ __global__ __launch_bounds__(kBlock) void k_corr_y_ring(Lattice lat, int n_r, ui
     const uint32_t r_max = sparse_r(n_r - 1);
     const int64_t rows_total = (int64_t)L + r_max;  // partner rows j = 0 .. L + r_max - 1
     const int64_t nchunks = (rows_total + kChunk - 1) / kChunk;
-    const int jr = threadIdx.x;
-    uint32_t ca[kSparseN], cb[kSparseN];
+    const int jr = threadIdx.x % kChunk;  // ring row of the chunk
+    const int sg = threadIdx.x / kChunk;  // separation group (wave-uniform)
+    const bool loader = sg == 0;          // the first kChunk threads move rows into the ring
+    uint32_t ca[kYPer], cb[kYPer];
 #pragma unroll
-    for (int q = 0; q < kSparseN; ++q) {
+    for (int q = 0; q < kYPer; ++q) {
         ca[q] = 0;
         cb[q] = 0;
     }
+    // A strip row is 16 bytes of each plane, an eighth of a 128-byte line.
+    // Blocks are dealt round-robin to the eight XCDs (block b on XCD b % 8),
+    // so when the strips are a whole number of lines and the grid a multiple
+    // of 64, the eight strips of one line go to eight blocks of the same XCD
+    // that walk down the lattice together: each line is fetched into that
+    // XCD's L2 once and read by all eight.  Otherwise strips are dealt out
+    // one by one.
+    const bool lines = strips % 8u == 0 && gridDim.x % 64u == 0;
+    const uint32_t per_iter = lines ? gridDim.x / 8u : gridDim.x;  // lines, or strips, per pass
+    const uint32_t total = lines ? strips / 8u : strips;
+    const uint32_t xcd = blockIdx.x % 8u, m = blockIdx.x / 8u;
+    const uint32_t first = lines ? xcd * (gridDim.x / 64u) + m / 8u : blockIdx.x;
     // global loads run one chunk ahead of the chunk being paired
-    for (uint32_t strip = blockIdx.x; strip < strips; strip += gridDim.x) {
+    for (uint32_t unit = first; unit < total; unit += per_iter) {
+        const uint32_t strip = lines ? unit * 8u + m % 8u : unit;
         const uint32_t w0 = strip * SW;
         auto load_row = [&](int64_t j, uint4 &p0, uint4 &p1) {
             const uint32_t jg = (uint32_t)(j % (int64_t)L);
@@ -257,22 +336,25 @@ __global__ __launch_bounds__(kBlock) void k_corr_y_ring(Lattice lat, int n_r, ui
             p0 = *reinterpret_cast<const uint4 *>(lat.planes + off);
             p1 = *reinterpret_cast<const uint4 *>(lat.planes + lat.plane_u32 + off);
         };
-        uint4 n0, n1;
+        uint4 n0{}, n1{};
         __syncthreads();
-        load_row(jr, n0, n1);
+        if (loader)
+            load_row(jr, n0, n1);
         for (int64_t ch = 0; ch < nchunks; ++ch) {
             const int64_t j0 = ch * kChunk;
             const uint32_t slot0 = (uint32_t)(j0 % (int64_t)RING);  // multiple of kChunk
-            uint4 *dst = reinterpret_cast<uint4 *>(ring + (size_t)(slot0 + jr) * kRingCols);
-            dst[0] = n0;
-            dst[1] = n1;
-            if (slot0 == 0) {
-                uint4 *mir = reinterpret_cast<uint4 *>(ring + (size_t)(RING + jr) * kRingCols);
-                mir[0] = n0;
-                mir[1] = n1;
+            if (loader) {
+                uint4 *dst = reinterpret_cast<uint4 *>(ring + (size_t)(slot0 + jr) * kRingCols);
+                dst[0] = n0;
+                dst[1] = n1;
+                if (slot0 == 0) {
+                    uint4 *mir = reinterpret_cast<uint4 *>(ring + (size_t)(RING + jr) * kRingCols);
+                    mir[0] = n0;
+                    mir[1] = n1;
+                }
             }
             __syncthreads();
-            if (ch + 1 < nchunks)
+            if (loader && ch + 1 < nchunks)
                 load_row(j0 + kChunk + jr, n0, n1);
             const int64_t j = j0 + jr;
             const Row8 x = lds_row(ring, slot0 + (uint32_t)jr);
@@ -280,15 +362,13 @@ __global__ __launch_bounds__(kBlock) void k_corr_y_ring(Lattice lat, int n_r, ui
             // of the set and j0 + kChunk - 1 - r < L for r = 1
             const bool all_valid = j0 >= (int64_t)sparse_r(kSparseN - 1) && j0 + kChunk - 1 < (int64_t)L + 1;
             if (all_valid)
-                y_pairs<MODEL, true, 0>(ring, slot0, jr, x, j, L, RING, ca, cb);
+                y_group<MODEL, true>(sg, ring, slot0, jr, x, j, L, RING, ca, cb);
             else
-                y_pairs<MODEL, false, 0>(ring, slot0, jr, x, j, L, RING, ca, cb);
+                y_group<MODEL, false>(sg, ring, slot0, jr, x, j, L, RING, ca, cb);
             __syncthreads();
         }
     }
-    if (MODEL != kIsing)
-        flush_counts<kSparseN>(ca, n_r, acc, 2);
-    flush_counts<kSparseN>(cb, n_r, acc + 1, 2);
+    flush_groups<MODEL != kIsing, kYPer>(ca, cb, sg, n_r, acc);
 }
 
 } // namespace
@@ -336,12 +416,12 @@ hipError_t launch_corr_sparse(const Lattice &lat, bool vertical, int n_r, unsign
     const uint32_t RING = (r_max + kChunk + kChunk - 1) / kChunk * kChunk;
     const size_t lds = (size_t)(RING + kChunk) * kRingCols * sizeof(uint32_t);
     if (lat.model == kIsing) {
-        const dim3 grid(corr_grid(lat.W / YShape<kIsing>::SW, 256)), block(kBlock);
+        const dim3 grid(corr_grid(lat.W / YShape<kIsing>::SW, 256)), block(kYThreads);
         (void)hipFuncSetAttribute((const void *)k_corr_y_ring<kIsing>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(k_corr_y_ring<kIsing>, grid, block, lds, st, lat, n_r, RING, acc);
     } else {
-        const dim3 grid(corr_grid(lat.W / YShape<kBlumeCapel>::SW, 256)), block(kBlock);
+        const dim3 grid(corr_grid(lat.W / YShape<kBlumeCapel>::SW, 256)), block(kYThreads);
         (void)hipFuncSetAttribute((const void *)k_corr_y_ring<kBlumeCapel>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(k_corr_y_ring<kBlumeCapel>, grid, block, lds, st, lat, n_r, RING, acc);
