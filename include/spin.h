@@ -163,7 +163,8 @@ int spin_threshold_table(int model, double J, double Delta, double T, uint32_t *
  *   1: 4 rows per thread; Ising words still undecided after 8 planes go
  *      to a per-wavefront work list that the wavefront drains together
  *   2: 8 rows per thread, work list        3: 4 rows per thread, per word
- * spin_set_variant sets one (-EINVAL outside 0..3); spin_tune times every
+ *   4: as 2 with a 16-slot list (the other undecided words finish in place)
+ * spin_set_variant sets one (-EINVAL outside 0..4); spin_tune times every
  * strategy on a scratch lattice of the handle's model and size (capped at
  * L = 32768; allocated and freed by the call) at bath temperature T, after
  * 16 warm-up sweeps from a T = infinity start, best of three interleaved

@@ -122,12 +122,14 @@ __global__ __launch_bounds__(kBlock) void k_init_bc(uint32_t *planes, uint32_t L
 // not for every word of a wavefront that holds one slow word.  Every site
 // ends with the outcome that all 32 planes define.
 constexpr int kWaves = kBlock / 64;
-constexpr int kListCap = 128;  // list slots per wavefront; later words finish in place
 
+// CAP list slots per wavefront; words past the last slot finish in place.
+template <int CAP>
 struct WaveList {
-    uint32_t und[kWaves][kListCap], acc[kWaves][kListCap];
-    uint32_t m3[kWaves][kListCap], m4[kWaves][kListCap], s[kWaves][kListCap];
-    uint16_t slot[kWaves][kListCap];  // row offset << 6 | owning lane
+    static constexpr int kCap = CAP;
+    uint32_t und[kWaves][CAP], acc[kWaves][CAP];
+    uint32_t m3[kWaves][CAP], m4[kWaves][CAP], s[kWaves][CAP];
+    uint16_t slot[kWaves][CAP];  // row offset << 6 | owning lane
     uint32_t i0[kWaves][64], w[kWaves][64];
 };
 
@@ -169,10 +171,11 @@ __device__ __forceinline__ void ising_em(unsigned long long (&e)[kEmCounters], u
     e[3] += __popc(ns ^ up) + __popc(ns ^ dn) + __popc(ns ^ cur) + __popc(ns ^ side);
 }
 
-template <bool MEASURE, int R, bool UNIFORM>
+template <bool MEASURE, int R, bool UNIFORM, typename List>
 __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t c, uint32_t t, const GroupTable &gt,
-                                                   uint64_t tile, WaveList &Q, unsigned long long (&e)[kEmCounters])
+                                                   uint64_t tile, List &Q, unsigned long long (&e)[kEmCounters])
 {
+    constexpr int kListCap = List::kCap;
     const uint32_t L = lat.L, W = lat.W;
     uint32_t *own = lat.planes + (c ? lat.plane_u32 : 0);
     const uint32_t *oth = lat.planes + (c ? 0 : lat.plane_u32);
@@ -379,9 +382,111 @@ __device__ __forceinline__ Pair load_pair(const uint32_t *plane, size_t word)
     return Pair{v.x, v.y};
 }
 
-// Blume-Capel half-sweep of one tile: per word the proposal plane, the
-// bit-sliced y = s_eff * h (neighbour sum seen from the sign that the move
-// carries), the 13 acceptance groups and the lazy Metropolis test.
+// Blume-Capel site classes of one word.  X is the proposal plane (plane 0 of
+// the proposal stream): the bit-sliced y = s_eff * h (neighbour sum seen from
+// the sign that the move carries) and the move family give each site its
+// acceptance group; need[q] are the sites of group q that need a random
+// number, never the sites that are always rejected (T = 0); the rest are
+// accepted outright.
+template <int NG>
+__device__ __forceinline__ void bc_classify(const GroupTable &gt, const Pair &s, const Pair (&nbr)[4], uint32_t X,
+                                            uint32_t (&need)[NG], uint32_t &never)
+{
+    // sign carried by y: that of s when s != 0, of the proposed s' when s = 0
+    const uint32_t neg = (s.z & s.s) | (~s.z & X);
+    uint32_t bits[8];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        const uint32_t anti = nbr[n].s ^ neg;
+        bits[n] = nbr[n].z & ~anti;        // neighbour contributes +1 to y
+        bits[4 + n] = ~(nbr[n].z & anti);  // neighbour does not contribute -1
+    }
+    uint32_t b0, b1, b2, b3;
+    count8(bits, b0, b1, b2, b3);  // v = y + 4 in [0, 8]
+    uint32_t Y[9];
+    {
+        const uint32_t nb3 = ~b3;
+        const uint32_t t0 = ~b1 & ~b0, t1 = ~b1 & b0, t2 = b1 & ~b0, t3 = b1 & b0;
+        const uint32_t h0 = nb3 & ~b2, h1 = nb3 & b2;
+        Y[0] = h0 & t0; Y[1] = h0 & t1; Y[2] = h0 & t2; Y[3] = h0 & t3;
+        Y[4] = h1 & t0; Y[5] = h1 & t1; Y[6] = h1 & t2; Y[7] = h1 & t3;
+        Y[8] = b3;
+    }
+    const uint32_t famA = s.z & ~X;  // s -> 0:   dE = J y - Delta
+    const uint32_t famB = ~s.z;      // 0 -> s':  dE = -J y + Delta
+    const uint32_t famC = s.z & X;   // s -> -s:  dE = 2 J y
+    uint32_t mask[NG];
+    if constexpr (NG == kBcGroups) {
+        // general Delta: for each y one of {s -> 0, 0 -> s'} can have dE > 0
+        // (sel_a picks it); s -> -s has dE > 0 for y > 0
+#pragma unroll
+        for (int q = 0; q < NG; ++q)
+            mask[q] = q < 9 ? ((((gt.sel_a_bits >> q) & 1u) ? famA : famB) & Y[q]) : (famC & Y[q - 4]);
+    } else {
+        // Delta = 0: dE = J y (s -> 0), -J y (0 -> s'), 2 J y (s -> -s); v = y + 4
+        mask[0] = (famA & Y[5]) | (famB & Y[3]);                 // dE = J
+        mask[1] = (famA & Y[6]) | (famB & Y[2]) | (famC & Y[5]);  // 2J
+        mask[2] = (famA & Y[7]) | (famB & Y[1]);                 // 3J
+        mask[3] = (famA & Y[8]) | (famB & Y[0]) | (famC & Y[6]);  // 4J
+        mask[4] = famC & Y[7];                                   // 6J
+        mask[5] = famC & Y[8];                                   // 8J
+    }
+    never = 0;
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+        need[q] = ((gt.rng_bits >> q) & 1u) ? mask[q] : 0u;
+        never |= ((gt.never_bits >> q) & 1u) ? mask[q] : 0u;
+    }
+}
+
+// New state of a word: accepted sites (F) take the proposed value.
+__device__ __forceinline__ Pair bc_new_state(uint32_t F, const Pair &s, uint32_t X)
+{
+    const uint32_t zp = ~s.z | X;          // proposed s' != 0
+    const uint32_t sp = X & ~(s.z & s.s);  // proposed s' < 0
+    return Pair{(F & zp) | (~F & s.z), (F & sp) | (~F & s.s)};
+}
+
+__device__ __forceinline__ void bc_store(uint32_t *own, size_t idx, const Pair &p)
+{
+    uint2 out;
+    out.x = p.z;
+    out.y = p.s;
+    reinterpret_cast<uint2 *>(own)[idx] = out;
+}
+
+// Energy/magnetisation counters of one updated word and the other-colour word
+// at its position (see kEmCounters).
+__device__ __forceinline__ void bc_em(unsigned long long (&e)[kEmCounters], const Pair &n, const Pair &cur,
+                                      const Pair (&nbr)[4])
+{
+    e[0] += __popc(n.z) + __popc(cur.z);
+    e[1] += __popc(n.s) + __popc(cur.s);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t both = n.z & nbr[k].z;
+        e[2] += __popc(both);
+        e[3] += __popc(both & (n.s ^ nbr[k].s));
+    }
+}
+
+// Neighbour pairs of word (i, w) of the other plane: up, down, same, side.
+__device__ __forceinline__ void bc_nbrs(const uint32_t *oth, uint32_t L, uint32_t W, uint32_t c, uint32_t i,
+                                        uint32_t w, Pair (&nbr)[4])
+{
+    const uint32_t iu = i == 0 ? L - 1 : i - 1, id = i + 1 == L ? 0 : i + 1;
+    const uint32_t odd = (i + c) & 1u;
+    const uint32_t wn = odd ? (w + 1u == W ? 0u : w + 1u) : (w == 0 ? W : w) - 1u;
+    nbr[0] = load_pair(oth, (size_t)iu * W + w);
+    nbr[1] = load_pair(oth, (size_t)id * W + w);
+    nbr[2] = load_pair(oth, (size_t)i * W + w);
+    const Pair nb = load_pair(oth, (size_t)i * W + wn);
+    nbr[3] = Pair{side_word(nbr[2].z, nb.z, odd), side_word(nbr[2].s, nb.s, odd)};
+}
+
+// Blume-Capel half-sweep of one tile, one word at a time: each thread runs
+// the lazy Metropolis test of its word to completion.  Each row loads the
+// next row's words before it draws random planes.
 template <bool MEASURE, int R, int NG>
 __device__ __forceinline__ void bc_tile(const Lattice &lat, uint32_t c, uint32_t t, const GroupTable &gt,
                                         uint64_t tile, unsigned long long (&e)[kEmCounters])
@@ -404,89 +509,179 @@ __device__ __forceinline__ void bc_tile(const Lattice &lat, uint32_t c, uint32_t
     const uint32_t wr = (w + 1u == W) ? 0u : w + 1u;
     Pair up = load_pair(oth, (size_t)(i0 == 0 ? L - 1 : i0 - 1) * W + w);
     Pair cur = load_pair(oth, (size_t)i0 * W + w);
+    Pair dn = load_pair(oth, (size_t)(i0 + 1u == L ? 0u : i0 + 1u) * W + w);
+    Pair nbw = load_pair(oth, (size_t)i0 * W + (((i0 + c) & 1u) ? wr : wl));
+    Pair s = load_pair(own, (size_t)i0 * W + w);
 #pragma unroll 2
     for (int r = 0; r < R; ++r) {
         const uint32_t i = i0 + (uint32_t)r;
-        const uint32_t inext = (i + 1u == L) ? 0u : i + 1u;
-        const Pair dn = load_pair(oth, (size_t)inext * W + w);
+        Pair dn2{0u, 0u}, nbw2{0u, 0u}, s2{0u, 0u};
+        if (r + 1 < R) {
+            const uint32_t i1 = i + 1u;  // i0 + R <= L: still in the tile
+            dn2 = load_pair(oth, (size_t)(i1 + 1u == L ? 0u : i1 + 1u) * W + w);
+            nbw2 = load_pair(oth, (size_t)i1 * W + (((i1 + c) & 1u) ? wr : wl));
+            s2 = load_pair(own, (size_t)i1 * W + w);
+        }
         const uint32_t odd = (i + c) & 1u;
-        const Pair nbw = load_pair(oth, (size_t)i * W + (odd ? wr : wl));
         const Pair side{side_word(cur.z, nbw.z, odd), side_word(cur.s, nbw.s, odd)};
-        const size_t idx = (size_t)i * W + w;
-        const Pair s = load_pair(own, idx);
-        // proposal bit per site: plane 0 of the proposal stream
-        const uint32_t X = philox4x32_10(i, w, t, stream_tag(kPurposePropose, c, 0), lat.key0, lat.key1).v[0];
-        // sign carried by y: that of s when s != 0, of the proposed s' when s = 0
-        const uint32_t neg = (s.z & s.s) | (~s.z & X);
         const Pair nbr[4] = {up, dn, cur, side};
-        uint32_t bits[8];
+        const uint32_t X = philox4x32_10(i, w, t, stream_tag(kPurposePropose, c, 0), lat.key0, lat.key1).v[0];
+        uint32_t need[NG], never;
+        bc_classify<NG>(gt, s, nbr, X, need, never);
+        uint32_t any = 0;
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            const uint32_t anti = nbr[n].s ^ neg;
-            bits[n] = nbr[n].z & ~anti;        // neighbour contributes +1 to y
-            bits[4 + n] = ~(nbr[n].z & anti);  // neighbour does not contribute -1
-        }
-        uint32_t b0, b1, b2, b3;
-        count8(bits, b0, b1, b2, b3);  // v = y + 4 in [0, 8]
-        uint32_t Y[9];
-        {
-            const uint32_t nb3 = ~b3;
-            const uint32_t t0 = ~b1 & ~b0, t1 = ~b1 & b0, t2 = b1 & ~b0, t3 = b1 & b0;
-            const uint32_t h0 = nb3 & ~b2, h1 = nb3 & b2;
-            Y[0] = h0 & t0; Y[1] = h0 & t1; Y[2] = h0 & t2; Y[3] = h0 & t3;
-            Y[4] = h1 & t0; Y[5] = h1 & t1; Y[6] = h1 & t2; Y[7] = h1 & t3;
-            Y[8] = b3;
-        }
-        const uint32_t famA = s.z & ~X;  // s -> 0:   dE = J y - Delta
-        const uint32_t famB = ~s.z;      // 0 -> s':  dE = -J y + Delta
-        const uint32_t famC = s.z & X;   // s -> -s:  dE = 2 J y
-        uint32_t mask[NG];
-        if constexpr (NG == kBcGroups) {
-            // general Delta: for each y one of {s -> 0, 0 -> s'} can have dE > 0
-            // (sel_a picks it); s -> -s has dE > 0 for y > 0
-#pragma unroll
-            for (int q = 0; q < NG; ++q)
-                mask[q] = q < 9 ? ((((gt.sel_a_bits >> q) & 1u) ? famA : famB) & Y[q]) : (famC & Y[q - 4]);
-        } else {
-            // Delta = 0: dE = J y (s -> 0), -J y (0 -> s'), 2 J y (s -> -s); v = y + 4
-            mask[0] = (famA & Y[5]) | (famB & Y[3]);                 // dE = J
-            mask[1] = (famA & Y[6]) | (famB & Y[2]) | (famC & Y[5]);  // 2J
-            mask[2] = (famA & Y[7]) | (famB & Y[1]);                 // 3J
-            mask[3] = (famA & Y[8]) | (famB & Y[0]) | (famC & Y[6]);  // 4J
-            mask[4] = famC & Y[7];                                   // 6J
-            mask[5] = famC & Y[8];                                   // 8J
-        }
-        uint32_t need[NG];
-        uint32_t never = 0, any = 0;
-#pragma unroll
-        for (int q = 0; q < NG; ++q) {
-            need[q] = ((gt.rng_bits >> q) & 1u) ? mask[q] : 0u;
-            never |= ((gt.never_bits >> q) & 1u) ? mask[q] : 0u;
+        for (int q = 0; q < NG; ++q)
             any |= need[q];
-        }
-        const uint32_t always = ~(any | never);
-        const uint32_t F = metropolis_accept<NG>(need, thr, always, i, w, t, c, lat.key0, lat.key1);
-        const uint32_t zp = ~s.z | X;          // proposed s' != 0
-        const uint32_t sp = X & ~(s.z & s.s);  // proposed s' < 0
-        const uint32_t nz = (F & zp) | (~F & s.z);
-        const uint32_t ns = (F & sp) | (~F & s.s);
-        uint2 out;
-        out.x = nz;
-        out.y = ns;
-        reinterpret_cast<uint2 *>(own)[idx] = out;
-        if (MEASURE) {
-            e[0] += __popc(nz) + __popc(cur.z);
-            e[1] += __popc(ns) + __popc(cur.s);
-#pragma unroll
-            for (int n = 0; n < 4; ++n) {
-                const uint32_t both = nz & nbr[n].z;
-                e[2] += __popc(both);
-                e[3] += __popc(both & (ns ^ nbr[n].s));
-            }
-        }
+        const uint32_t F = metropolis_accept<NG>(need, thr, ~(any | never), i, w, t, c, lat.key0, lat.key1);
+        const Pair n = bc_new_state(F, s, X);
+        bc_store(own, (size_t)i * W + w, n);
+        if (MEASURE)
+            bc_em(e, n, cur, nbr);
         up = cur;
         cur = dn;
+        dn = dn2;
+        nbw = nbw2;
+        s = s2;
     }
+}
+
+// Blume-Capel half-sweep, compacting form (as ising_tile_compact): proposal
+// plane and acceptance blocks 0 and 1 in place, words still undecided after
+// eight planes to the wavefront's list, drained one word per lane.
+template <int NG, int CAP>
+struct BcList {
+    static constexpr int kCap = CAP;
+    uint32_t und[kWaves][CAP], acc[kWaves][CAP], z[kWaves][CAP], s[kWaves][CAP], x[kWaves][CAP];
+    uint32_t need[NG][kWaves][CAP];
+    uint16_t slot[kWaves][CAP];  // row offset << 6 | owning lane
+    uint32_t i0[kWaves][64], w[kWaves][64];
+};
+
+template <bool MEASURE, int R, int NG, typename List>
+__device__ __forceinline__ void bc_tile_compact(const Lattice &lat, uint32_t c, uint32_t t, const GroupTable &gt,
+                                                uint64_t tile, List &Q, unsigned long long (&e)[kEmCounters])
+{
+    constexpr int kListCap = List::kCap;
+    const uint32_t L = lat.L, W = lat.W;
+    uint32_t *own = lat.planes + (c ? lat.plane_u32 : 0);
+    const uint32_t *oth = lat.planes + (c ? 0 : lat.plane_u32);
+    const uint64_t nitems = (uint64_t)(L / R) * W;
+    uint32_t thr[NG];
+#pragma unroll
+    for (int q = 0; q < NG; ++q)
+        thr[q] = gt.thr[q];
+    const uint32_t k0 = lat.key0, k1 = lat.key1;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint64_t g = tile * kBlock + threadIdx.x;
+    const bool valid = g < nitems;
+    const uint32_t rg = valid ? (uint32_t)(g / W) : 0u;
+    const uint32_t w = valid ? (uint32_t)(g - (uint64_t)rg * W) : 0u;
+    const uint32_t i0 = rg * R;
+    Q.i0[wave][lane] = i0;
+    Q.w[wave][lane] = w;
+    uint32_t n = 0;
+    const uint32_t wl = (w == 0 ? W : w) - 1u;
+    const uint32_t wr = (w + 1u == W) ? 0u : w + 1u;
+    // lanes past the end (rg = w = 0) load existing words and never use them
+    Pair up = load_pair(oth, (size_t)(i0 == 0 ? L - 1 : i0 - 1) * W + w);
+    Pair cur = load_pair(oth, (size_t)i0 * W + w);
+    Pair dn = load_pair(oth, (size_t)(i0 + 1u == L ? 0u : i0 + 1u) * W + w);
+    Pair nbw = load_pair(oth, (size_t)i0 * W + (((i0 + c) & 1u) ? wr : wl));
+    Pair s = load_pair(own, (size_t)i0 * W + w);
+#pragma unroll 2
+    for (int r = 0; r < R; ++r) {
+        const uint32_t i = i0 + (uint32_t)r;
+        Pair dn2{0u, 0u}, nbw2{0u, 0u}, s2{0u, 0u};
+        if (r + 1 < R) {
+            const uint32_t i1 = i + 1u;  // i0 + R <= L: still in the tile
+            dn2 = load_pair(oth, (size_t)(i1 + 1u == L ? 0u : i1 + 1u) * W + w);
+            nbw2 = load_pair(oth, (size_t)i1 * W + (((i1 + c) & 1u) ? wr : wl));
+            s2 = load_pair(own, (size_t)i1 * W + w);
+        }
+        const uint32_t odd = (i + c) & 1u;
+        const Pair side{side_word(cur.z, nbw.z, odd), side_word(cur.s, nbw.s, odd)};
+        const Pair nbr[4] = {up, dn, cur, side};
+        uint32_t X = 0, acc = 0, und = 0, need[NG];
+#pragma unroll
+        for (int q = 0; q < NG; ++q)
+            need[q] = 0;
+        if (valid) {
+            X = philox4x32_10(i, w, t, stream_tag(kPurposePropose, c, 0), k0, k1).v[0];
+            uint32_t never;
+            bc_classify<NG>(gt, s, nbr, X, need, never);
+#pragma unroll
+            for (int q = 0; q < NG; ++q)
+                und |= need[q];
+            acc = ~(und | never);
+            if (und != 0u) {
+                const Block4 b = philox4x32_10(i, w, t, stream_tag(kPurposeAccept, c, 0), k0, k1);
+                apply_block<NG>(b, 0u, need, thr, und, acc);
+            }
+            if (und != 0u) {
+                const Block4 b = philox4x32_10(i, w, t, stream_tag(kPurposeAccept, c, 1), k0, k1);
+                apply_block<NG>(b, 1u, need, thr, und, acc);
+            }
+        }
+        const unsigned long long bal = __ballot(und != 0u);
+        bool listed = false;
+        if (und != 0u) {
+            const uint32_t p = n + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            if (p < (uint32_t)kListCap) {
+                Q.und[wave][p] = und;
+                Q.acc[wave][p] = acc;
+                Q.z[wave][p] = s.z;
+                Q.s[wave][p] = s.s;
+                Q.x[wave][p] = X;
+#pragma unroll
+                for (int q = 0; q < NG; ++q)
+                    Q.need[q][wave][p] = need[q];
+                Q.slot[wave][p] = (uint16_t)(((uint32_t)r << 6) | lane);
+                listed = true;
+            } else {
+                for (uint32_t blk = 2; blk < 8u && und != 0u; ++blk) {
+                    const Block4 b = philox4x32_10(i, w, t, stream_tag(kPurposeAccept, c, blk), k0, k1);
+                    apply_block<NG>(b, blk, need, thr, und, acc);
+                }
+            }
+        }
+        if (valid && !listed) {
+            const Pair ns = bc_new_state(acc, s, X);  // ties after 32 planes (u == thr) rejected
+            bc_store(own, (size_t)i * W + w, ns);
+            if (MEASURE)
+                bc_em(e, ns, cur, nbr);
+        }
+        n += (uint32_t)__popcll(bal);
+        up = cur;
+        cur = dn;
+        dn = dn2;
+        nbw = nbw2;
+        s = s2;
+    }
+    if (n > (uint32_t)kListCap)
+        n = kListCap;
+    wave_sync();
+    for (uint32_t k = lane; k < n; k += 64u) {
+        const uint32_t slot = Q.slot[wave][k], owner = slot & 63u;
+        const uint32_t i = Q.i0[wave][owner] + (slot >> 6), wq = Q.w[wave][owner];
+        uint32_t need[NG];
+#pragma unroll
+        for (int q = 0; q < NG; ++q)
+            need[q] = Q.need[q][wave][k];
+        uint32_t und = Q.und[wave][k], acc = Q.acc[wave][k];
+        for (uint32_t blk = 2; blk < 8u && und != 0u; ++blk) {
+            const Block4 b = philox4x32_10(i, wq, t, stream_tag(kPurposeAccept, c, blk), k0, k1);
+            apply_block<NG>(b, blk, need, thr, und, acc);
+        }
+        const Pair ns = bc_new_state(acc, Pair{Q.z[wave][k], Q.s[wave][k]}, Q.x[wave][k]);
+        bc_store(own, (size_t)i * W + wq, ns);
+        if (MEASURE) {
+            Pair nbr[4];
+            bc_nbrs(oth, L, W, c, i, wq, nbr);
+            bc_em(e, ns, nbr[2], nbr);
+        }
+    }
+    wave_sync();  // the list is refilled by the next tile
 }
 
 template <int R>
@@ -494,6 +689,21 @@ __host__ __device__ inline uint64_t tiles_of(const Lattice &lat)
 {
     return ((uint64_t)(lat.L / R) * lat.W + kBlock - 1) / kBlock;
 }
+
+// LDS of the compacting tiles: one list per model and group count, sharing
+// storage (a launch uses one of them at a time per tile).
+template <int CAP>
+union BcListUnion {
+    BcList<kBcGroupsDelta0, CAP> d0;
+    BcList<kBcGroups, CAP> gen;
+};
+
+template <int CAP>
+union AnyList {
+    WaveList<CAP> ising;
+    BcList<kBcGroupsDelta0, CAP> d0;
+    BcList<kBcGroups, CAP> gen;
+};
 
 template <bool MEASURE, int V>
 __global__ __launch_bounds__(kBlock) void k_sweep_ising(Lattice lat, uint32_t c, uint32_t t, GroupTable gt,
@@ -503,7 +713,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_ising(Lattice lat, uint32_t c,
     unsigned long long e[kEmCounters] = {0, 0, 0, 0};
     const uint64_t ntiles = tiles_of<R>(lat);
     if constexpr (variant_compact(V)) {
-        __shared__ WaveList Q;
+        __shared__ WaveList<variant_list_cap(V)> Q;
         if (lat.W % kBlock == 0) {
             for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
                 ising_tile_compact<MEASURE, R, true>(lat, c, t, gt, tile, Q, e);
@@ -529,7 +739,16 @@ __global__ __launch_bounds__(kBlock) void k_sweep_bc(Lattice lat, uint32_t c, ui
     constexpr int R = variant_rows(V);
     unsigned long long e[kEmCounters] = {0, 0, 0, 0};
     const uint64_t ntiles = tiles_of<R>(lat);
-    if (lat.bc_groups == kBcGroupsDelta0) {
+    if constexpr (variant_compact(V)) {
+        __shared__ BcListUnion<variant_list_cap(V)> Q;
+        if (lat.bc_groups == kBcGroupsDelta0) {
+            for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+                bc_tile_compact<MEASURE, R, kBcGroupsDelta0>(lat, c, t, gt, tile, Q.d0, e);
+        } else {
+            for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+                bc_tile_compact<MEASURE, R, kBcGroups>(lat, c, t, gt, tile, Q.gen, e);
+        }
+    } else if (lat.bc_groups == kBcGroupsDelta0) {
         for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
             bc_tile<MEASURE, R, kBcGroupsDelta0>(lat, c, t, gt, tile, e);
     } else {
@@ -550,7 +769,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica 
                                                              uint32_t stride, uint32_t step, uint32_t c)
 {
     constexpr int R = variant_rows(V);
-    __shared__ std::conditional_t<variant_compact(V), WaveList, int> Q;
+    __shared__ std::conditional_t<variant_compact(V), AnyList<variant_list_cap(V)>, int> Q;
     unsigned long long e[kEmCounters] = {0, 0, 0, 0};
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const uint32_t rid = tile_rep[tile];
@@ -558,13 +777,18 @@ __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica 
         const GroupTable &gt = tables[(size_t)rep.sched * stride + step];
         const uint64_t local = tile - rep.tile0;
         const uint32_t t = rep.t0 + step;
-        if (rep.lat.model == kIsing) {
-            if constexpr (variant_compact(V)) {
+        if constexpr (variant_compact(V)) {
+            if (rep.lat.model == kIsing) {
                 if (rep.lat.W % kBlock == 0)
-                    ising_tile_compact<false, R, true>(rep.lat, c, t, gt, local, Q, e);
+                    ising_tile_compact<false, R, true>(rep.lat, c, t, gt, local, Q.ising, e);
                 else
-                    ising_tile_compact<false, R, false>(rep.lat, c, t, gt, local, Q, e);
-            } else if (rep.lat.W % kBlock == 0)
+                    ising_tile_compact<false, R, false>(rep.lat, c, t, gt, local, Q.ising, e);
+            } else if (rep.lat.bc_groups == kBcGroupsDelta0)
+                bc_tile_compact<false, R, kBcGroupsDelta0>(rep.lat, c, t, gt, local, Q.d0, e);
+            else
+                bc_tile_compact<false, R, kBcGroups>(rep.lat, c, t, gt, local, Q.gen, e);
+        } else if (rep.lat.model == kIsing) {
+            if (rep.lat.W % kBlock == 0)
                 ising_tile_lazy<false, R, true>(rep.lat, c, t, gt, local, e);
             else
                 ising_tile_lazy<false, R, false>(rep.lat, c, t, gt, local, e);
@@ -788,6 +1012,8 @@ hipError_t launch_half_sweep(const Lattice &lat, uint32_t colour, uint32_t t, co
                      : launch_half_sweep_v<false, 2>(lat, colour, t, gt, em_acc, st);
     case 3: return m ? launch_half_sweep_v<true, 3>(lat, colour, t, gt, em_acc, st)
                      : launch_half_sweep_v<false, 3>(lat, colour, t, gt, em_acc, st);
+    case 4: return m ? launch_half_sweep_v<true, 4>(lat, colour, t, gt, em_acc, st)
+                     : launch_half_sweep_v<false, 4>(lat, colour, t, gt, em_acc, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -816,6 +1042,7 @@ hipError_t launch_batch_half_sweep(int variant, const BatchReplica *reps, const 
     case 1: return launch_batch_v<1>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
     case 2: return launch_batch_v<2>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
     case 3: return launch_batch_v<3>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
+    case 4: return launch_batch_v<4>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
     default: return hipErrorInvalidValue;
     }
 }

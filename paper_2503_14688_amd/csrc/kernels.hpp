@@ -38,14 +38,17 @@ struct Lattice {
     int variant;         // sweep strategy, see variant_rows / variant_compact
 };
 
-// Sweep strategies: rows walked per thread (4 or 8) and, for Ising, whether
-// words still undecided after eight planes go to the wavefront's LDS work
-// list (ising_tile_compact) or each thread finishes its word's lazy test
-// itself (ising_tile_lazy).  Blume-Capel uses the row count only.
+// Sweep strategies: rows walked per thread (4 or 8) and whether words still
+// undecided after eight planes go to the wavefront's LDS work list
+// (ising_tile_compact, bc_tile_compact) or each thread finishes its word's
+// lazy test itself (ising_tile_lazy, bc_tile).
 //   0: 8 rows, per word   1: 4 rows, compacting   2: 8 rows, compacting   3: 4 rows, per word
-constexpr int kVariants = 4;
+//   4: 8 rows, compacting with a 16-slot list (most undecided words finish in
+//      place; the same results, slower)
+constexpr int kVariants = 5;
 __host__ __device__ constexpr int variant_rows(int v) { return (v == 1 || v == 3) ? 4 : 8; }
-__host__ __device__ constexpr bool variant_compact(int v) { return v == 1 || v == 2; }
+__host__ __device__ constexpr bool variant_compact(int v) { return v == 1 || v == 2 || v == 4; }
+__host__ __device__ constexpr int variant_list_cap(int v) { return v == 4 ? 16 : 128; }
 
 // Counters of the energy/magnetisation reduction (both colours):
 //   acc[0] = #(s != 0)  acc[1] = #(s < 0)

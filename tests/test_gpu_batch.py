@@ -42,7 +42,7 @@ def oracle_run(rep, T_row, n):
     return s
 
 
-@pytest.mark.parametrize("flags", [0, 1 << 4, 2 << 4, 3 << 4, 4 << 4, 1 | (3 << 4), 1 | (2 << 4)])
+@pytest.mark.parametrize("flags", [0, 1 << 4, 2 << 4, 3 << 4, 4 << 4, 5 << 4, 1 | (3 << 4), 1 | (2 << 4)])
 def test_batch_matches_oracle(gpu, flags):
     reps = mixed_replicas()
     n = 16
@@ -51,7 +51,7 @@ def test_batch_matches_oracle(gpu, flags):
     b.run(n, flags)
     b.sync()
     info = b.info()
-    assert info["t"] == n and info["variant"] in (0, 1, 2, 3) and info["replicas"] == len(reps)
+    assert info["t"] == n and info["variant"] in range(5) and info["replicas"] == len(reps)
     for k, rep in enumerate(reps):
         assert np.array_equal(b.spins(k), oracle_run(rep, T[rep["schedule"]], n)), (k, rep)
     b.close()

@@ -207,14 +207,14 @@ def test_sparse_and_generic_correlation_kernels_agree(gpu, model, L):
 
 @pytest.mark.parametrize("model", [0, 1])
 def test_sweep_strategies_agree(gpu, model):
-    """All sweep strategies (rows per thread, per-word or queued random
-    planes) give the oracle's trajectory; the tuner picks one of them."""
+    """All sweep strategies (rows per thread, per-word or compacting lazy
+    test, list size) give the oracle's trajectory; the tuner picks one."""
     L, seed = 512, 77
     T = np.full(6, 2.2 if model == 0 else 1.7)
     s = oracle.init(model, L, seed)
     oracle.sweep(model, s, seed, 1.0, 0.0, 0, T)
     bond = oracle.measure(s, [])["bond"]
-    for v in range(4):
+    for v in range(5):
         lat = make(gpu, model, L, seed)
         lat.variant = v
         assert lat.variant == v
@@ -223,12 +223,31 @@ def test_sweep_strategies_agree(gpu, model):
         assert lat.measure()["bond"] == bond
         lat.close()
     lat = make(gpu, model, L, seed)
-    assert lat.tune(float(T[0])) in (0, 1, 2, 3)
+    assert lat.tune(float(T[0])) in range(5)
     lat.sweep(T)
     assert np.array_equal(lat.spins(), s)
     with pytest.raises(gpu.SpinError):
-        lat.variant = 4
+        lat.variant = 5
     lat.close()
+
+
+def test_uniform_row_tiles_all_strategies(gpu):
+    """L = 16384: a plane row is a whole number of 256-word tiles, so the Ising
+    sweep takes its row-uniform path (the path of the L = 2^20 workload).
+    Every strategy, including the 16-slot list whose overflow words finish in
+    place, reproduces the oracle's trajectory and bond sum."""
+    L, seed = 16384, 2024
+    T = np.full(3, workloads.TC_ISING)
+    s = oracle.init(0, L, seed)
+    oracle.sweep(0, s, seed, 1.0, 0.0, 0, T)
+    bond = oracle.measure(s, [])["bond"]
+    for v in range(5):
+        lat = make(gpu, 0, L, seed)
+        lat.variant = v
+        lat.sweep(T, fuse_measure=True)
+        assert lat.measure()["bond"] == bond, v
+        assert np.array_equal(lat.spins(), s), v
+        lat.close()
 
 
 def test_ising_L4096_check_run(gpu):
