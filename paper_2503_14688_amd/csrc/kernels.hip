@@ -128,9 +128,12 @@ template <int CAP>
 struct WaveList {
     static constexpr int kCap = CAP;
     uint32_t und[kWaves][CAP], acc[kWaves][CAP];
-    uint32_t m3[kWaves][CAP], m4[kWaves][CAP], s[kWaves][CAP];
+    uint32_t m3[kWaves][CAP], m4[kWaves][CAP];
     uint16_t slot[kWaves][CAP];  // row offset << 6 | owning lane
     uint32_t i0[kWaves][64], w[kWaves][64];
+    // new words of the tile, stored to HBM in whole rows once the list is
+    // drained (listed words hold the old word until then)
+    uint32_t stage[kWaves][8][64];
 };
 
 // Orders the LDS accesses of one wavefront's lanes (no cross-wave effect).
@@ -255,8 +258,8 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
                 Q.acc[wave][p] = acc;
                 Q.m3[wave][p] = need[0];
                 Q.m4[wave][p] = need[1];
-                Q.s[wave][p] = sv;
                 Q.slot[wave][p] = (uint16_t)(((uint32_t)r << 6) | lane);
+                Q.stage[wave][r][lane] = sv;
                 listed = true;
             } else {
                 for (uint32_t blk = 2; blk < 8u && und != 0u; ++blk) {
@@ -268,7 +271,7 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
         if (valid && !listed) {
             // sites still tied after 32 planes have u == thr: rejected
             const uint32_t ns = sv ^ acc;
-            own[(size_t)i * W + w] = ns;
+            Q.stage[wave][r][lane] = ns;
             if (MEASURE)
                 ising_em(e, ns, up, dn, cur, side);
         }
@@ -291,14 +294,21 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
             const Block4 b = philox4x32_10(i, wq, t, stream_tag(kPurposeAccept, c, blk), k0, k1);
             apply_block_2g(b, blk, need, thr, und, acc);
         }
-        const uint32_t ns = Q.s[wave][k] ^ acc;
-        own[(size_t)i * W + wq] = ns;
+        const uint32_t ns = Q.stage[wave][slot >> 6][owner] ^ acc;
+        Q.stage[wave][slot >> 6][owner] = ns;
         if (MEASURE) {
             const IsingNbrs nb = ising_nbrs(oth, L, W, c, i, wq);
             ising_em(e, ns, nb.up, nb.dn, nb.cur, nb.side);
         }
     }
-    wave_sync();  // the list is refilled by the next tile
+    wave_sync();
+    // whole rows to HBM: every line of the tile is written once and complete
+    if (valid) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            own[(size_t)(i0 + (uint32_t)r) * W + w] = Q.stage[wave][r][lane];
+    }
+    wave_sync();  // the list and the stage are refilled by the next tile
 }
 
 // Ising half-sweep of one tile, one word at a time: each thread runs the
