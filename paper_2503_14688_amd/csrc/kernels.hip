@@ -115,25 +115,28 @@ __global__ __launch_bounds__(kBlock) void k_init_bc(uint32_t *planes, uint32_t L
 
 // Ising half-sweep, compacting form.  Every word gets its classes and the
 // first two Philox blocks (planes 0-7) in place, which settles all sites of
-// about nine words in ten; those are written back at once.  The rest go to a
-// work list owned by the wavefront (ballot ranks, no block barrier); the
-// wavefront then drains the list with one word per lane and writes those
-// words, so the later blocks are drawn for the few words that need them and
-// not for every word of a wavefront that holds one slow word.  Every site
-// ends with the outcome that all 32 planes define.
+// about nine words in ten.  The rest go to a work list owned by the
+// wavefront (ballot ranks, no block barrier); the wavefront then drains the
+// list with one word per lane, so the later blocks are drawn for the few
+// words that need them and not for every word of a wavefront that holds one
+// slow word.  New words collect in LDS and go to HBM as whole rows at the end
+// of the tile.  Every site ends with the outcome that all 32 planes define.
 constexpr int kWaves = kBlock / 64;
 
-// CAP list slots per wavefront; words past the last slot finish in place.
+// One wavefront's list: CAP slots; words past the last slot finish in place.
+// A block holds one per wavefront, each a contiguous region, so wavefronts
+// that are at different tiles never touch each other's storage, whichever
+// list type each tile uses.
 template <int CAP>
 struct WaveList {
     static constexpr int kCap = CAP;
-    uint32_t und[kWaves][CAP], acc[kWaves][CAP];
-    uint32_t m3[kWaves][CAP], m4[kWaves][CAP];
-    uint16_t slot[kWaves][CAP];  // row offset << 6 | owning lane
-    uint32_t i0[kWaves][64], w[kWaves][64];
+    uint32_t und[CAP], acc[CAP];
+    uint32_t m3[CAP], m4[CAP];
+    uint16_t slot[CAP];  // row offset << 6 | owning lane
+    uint32_t i0[64], w[64];
     // new words of the tile, stored to HBM in whole rows once the list is
     // drained (listed words hold the old word until then)
-    uint32_t stage[kWaves][8][64];
+    uint32_t stage[8][64];
 };
 
 // Orders the LDS accesses of one wavefront's lanes (no cross-wave effect).
@@ -174,6 +177,7 @@ __device__ __forceinline__ void ising_em(unsigned long long (&e)[kEmCounters], u
     e[3] += __popc(ns ^ up) + __popc(ns ^ dn) + __popc(ns ^ cur) + __popc(ns ^ side);
 }
 
+// Q is the calling wavefront's own list.
 template <bool MEASURE, int R, bool UNIFORM, typename List>
 __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t c, uint32_t t, const GroupTable &gt,
                                                    uint64_t tile, List &Q, unsigned long long (&e)[kEmCounters])
@@ -187,7 +191,7 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
     const bool rng3 = gt.rng_bits & 1u, rng4 = gt.rng_bits & 2u;
     const bool nev3 = gt.never_bits & 1u, nev4 = gt.never_bits & 2u;
     const uint32_t k0 = lat.key0, k1 = lat.key1;
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t lane = threadIdx.x & 63u;
     const uint64_t g = tile * kBlock + threadIdx.x;
     const bool valid = g < nitems;
     uint32_t rg, w;
@@ -199,8 +203,8 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
         w = valid ? (uint32_t)(g - (uint64_t)rg * W) : 0u;
     }
     const uint32_t i0 = rg * R;
-    Q.i0[wave][lane] = i0;
-    Q.w[wave][lane] = w;
+    Q.i0[lane] = i0;
+    Q.w[lane] = w;
     uint32_t n = 0;
     const uint32_t wl = (w == 0 ? W : w) - 1u;
     const uint32_t wr = (w + 1u == W) ? 0u : w + 1u;
@@ -254,12 +258,12 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
             const uint32_t p = n + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
             if (p < (uint32_t)kListCap) {
-                Q.und[wave][p] = und;
-                Q.acc[wave][p] = acc;
-                Q.m3[wave][p] = need[0];
-                Q.m4[wave][p] = need[1];
-                Q.slot[wave][p] = (uint16_t)(((uint32_t)r << 6) | lane);
-                Q.stage[wave][r][lane] = sv;
+                Q.und[p] = und;
+                Q.acc[p] = acc;
+                Q.m3[p] = need[0];
+                Q.m4[p] = need[1];
+                Q.slot[p] = (uint16_t)(((uint32_t)r << 6) | lane);
+                Q.stage[r][lane] = sv;
                 listed = true;
             } else {
                 for (uint32_t blk = 2; blk < 8u && und != 0u; ++blk) {
@@ -271,7 +275,7 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
         if (valid && !listed) {
             // sites still tied after 32 planes have u == thr: rejected
             const uint32_t ns = sv ^ acc;
-            Q.stage[wave][r][lane] = ns;
+            Q.stage[r][lane] = ns;
             if (MEASURE)
                 ising_em(e, ns, up, dn, cur, side);
         }
@@ -286,16 +290,16 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
         n = kListCap;
     wave_sync();
     for (uint32_t k = lane; k < n; k += 64u) {
-        const uint32_t slot = Q.slot[wave][k], owner = slot & 63u;
-        const uint32_t i = Q.i0[wave][owner] + (slot >> 6), wq = Q.w[wave][owner];
-        const uint32_t need[2] = {Q.m3[wave][k], Q.m4[wave][k]};
-        uint32_t und = Q.und[wave][k], acc = Q.acc[wave][k];
+        const uint32_t slot = Q.slot[k], owner = slot & 63u;
+        const uint32_t i = Q.i0[owner] + (slot >> 6), wq = Q.w[owner];
+        const uint32_t need[2] = {Q.m3[k], Q.m4[k]};
+        uint32_t und = Q.und[k], acc = Q.acc[k];
         for (uint32_t blk = 2; blk < 8u && und != 0u; ++blk) {
             const Block4 b = philox4x32_10(i, wq, t, stream_tag(kPurposeAccept, c, blk), k0, k1);
             apply_block_2g(b, blk, need, thr, und, acc);
         }
-        const uint32_t ns = Q.stage[wave][slot >> 6][owner] ^ acc;
-        Q.stage[wave][slot >> 6][owner] = ns;
+        const uint32_t ns = Q.stage[slot >> 6][owner] ^ acc;
+        Q.stage[slot >> 6][owner] = ns;
         if (MEASURE) {
             const IsingNbrs nb = ising_nbrs(oth, L, W, c, i, wq);
             ising_em(e, ns, nb.up, nb.dn, nb.cur, nb.side);
@@ -306,7 +310,7 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
     if (valid) {
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            own[(size_t)(i0 + (uint32_t)r) * W + w] = Q.stage[wave][r][lane];
+            own[(size_t)(i0 + (uint32_t)r) * W + w] = Q.stage[r][lane];
     }
     wave_sync();  // the list and the stage are refilled by the next tile
 }
@@ -557,14 +561,18 @@ __device__ __forceinline__ void bc_tile(const Lattice &lat, uint32_t c, uint32_t
 
 // Blume-Capel half-sweep, compacting form (as ising_tile_compact): proposal
 // plane and acceptance blocks 0 and 1 in place, words still undecided after
-// eight planes to the wavefront's list, drained one word per lane.
-template <int NG, int CAP>
+// eight planes to the wavefront's list, drained one word per lane, new words
+// staged in LDS and stored as whole rows.
+template <int NG, int CAP, int R>
 struct BcList {
     static constexpr int kCap = CAP;
-    uint32_t und[kWaves][CAP], acc[kWaves][CAP], z[kWaves][CAP], s[kWaves][CAP], x[kWaves][CAP];
-    uint32_t need[NG][kWaves][CAP];
-    uint16_t slot[kWaves][CAP];  // row offset << 6 | owning lane
-    uint32_t i0[kWaves][64], w[kWaves][64];
+    uint32_t und[CAP], acc[CAP], x[CAP];
+    uint32_t need[NG][CAP];
+    uint16_t slot[CAP];  // row offset << 6 | owning lane
+    uint32_t i0[64], w[64];
+    // new (Z, S) words of the tile, stored to HBM in whole rows once the
+    // list is drained (listed words hold the old pair until then)
+    uint2 stage[R][64];
 };
 
 template <bool MEASURE, int R, int NG, typename List>
@@ -581,14 +589,14 @@ __device__ __forceinline__ void bc_tile_compact(const Lattice &lat, uint32_t c, 
     for (int q = 0; q < NG; ++q)
         thr[q] = gt.thr[q];
     const uint32_t k0 = lat.key0, k1 = lat.key1;
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t lane = threadIdx.x & 63u;
     const uint64_t g = tile * kBlock + threadIdx.x;
     const bool valid = g < nitems;
     const uint32_t rg = valid ? (uint32_t)(g / W) : 0u;
     const uint32_t w = valid ? (uint32_t)(g - (uint64_t)rg * W) : 0u;
     const uint32_t i0 = rg * R;
-    Q.i0[wave][lane] = i0;
-    Q.w[wave][lane] = w;
+    Q.i0[lane] = i0;
+    Q.w[lane] = w;
     uint32_t n = 0;
     const uint32_t wl = (w == 0 ? W : w) - 1u;
     const uint32_t wr = (w + 1u == W) ? 0u : w + 1u;
@@ -638,15 +646,14 @@ __device__ __forceinline__ void bc_tile_compact(const Lattice &lat, uint32_t c, 
             const uint32_t p = n + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
             if (p < (uint32_t)kListCap) {
-                Q.und[wave][p] = und;
-                Q.acc[wave][p] = acc;
-                Q.z[wave][p] = s.z;
-                Q.s[wave][p] = s.s;
-                Q.x[wave][p] = X;
+                Q.und[p] = und;
+                Q.acc[p] = acc;
+                Q.x[p] = X;
+                Q.stage[r][lane] = make_uint2(s.z, s.s);
 #pragma unroll
                 for (int q = 0; q < NG; ++q)
-                    Q.need[q][wave][p] = need[q];
-                Q.slot[wave][p] = (uint16_t)(((uint32_t)r << 6) | lane);
+                    Q.need[q][p] = need[q];
+                Q.slot[p] = (uint16_t)(((uint32_t)r << 6) | lane);
                 listed = true;
             } else {
                 for (uint32_t blk = 2; blk < 8u && und != 0u; ++blk) {
@@ -657,7 +664,7 @@ __device__ __forceinline__ void bc_tile_compact(const Lattice &lat, uint32_t c, 
         }
         if (valid && !listed) {
             const Pair ns = bc_new_state(acc, s, X);  // ties after 32 planes (u == thr) rejected
-            bc_store(own, (size_t)i * W + w, ns);
+            Q.stage[r][lane] = make_uint2(ns.z, ns.s);
             if (MEASURE)
                 bc_em(e, ns, cur, nbr);
         }
@@ -672,26 +679,34 @@ __device__ __forceinline__ void bc_tile_compact(const Lattice &lat, uint32_t c, 
         n = kListCap;
     wave_sync();
     for (uint32_t k = lane; k < n; k += 64u) {
-        const uint32_t slot = Q.slot[wave][k], owner = slot & 63u;
-        const uint32_t i = Q.i0[wave][owner] + (slot >> 6), wq = Q.w[wave][owner];
+        const uint32_t slot = Q.slot[k], owner = slot & 63u;
+        const uint32_t i = Q.i0[owner] + (slot >> 6), wq = Q.w[owner];
         uint32_t need[NG];
 #pragma unroll
         for (int q = 0; q < NG; ++q)
-            need[q] = Q.need[q][wave][k];
-        uint32_t und = Q.und[wave][k], acc = Q.acc[wave][k];
+            need[q] = Q.need[q][k];
+        uint32_t und = Q.und[k], acc = Q.acc[k];
         for (uint32_t blk = 2; blk < 8u && und != 0u; ++blk) {
             const Block4 b = philox4x32_10(i, wq, t, stream_tag(kPurposeAccept, c, blk), k0, k1);
             apply_block<NG>(b, blk, need, thr, und, acc);
         }
-        const Pair ns = bc_new_state(acc, Pair{Q.z[wave][k], Q.s[wave][k]}, Q.x[wave][k]);
-        bc_store(own, (size_t)i * W + wq, ns);
+        const uint2 old = Q.stage[slot >> 6][owner];
+        const Pair ns = bc_new_state(acc, Pair{old.x, old.y}, Q.x[k]);
+        Q.stage[slot >> 6][owner] = make_uint2(ns.z, ns.s);
         if (MEASURE) {
             Pair nbr[4];
             bc_nbrs(oth, L, W, c, i, wq, nbr);
             bc_em(e, ns, nbr[2], nbr);
         }
     }
-    wave_sync();  // the list is refilled by the next tile
+    wave_sync();
+    // whole rows to HBM: every line of the tile is written once and complete
+    if (valid) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            reinterpret_cast<uint2 *>(own)[(size_t)(i0 + (uint32_t)r) * W + w] = Q.stage[r][lane];
+    }
+    wave_sync();  // the list and the stage are refilled by the next tile
 }
 
 template <int R>
@@ -700,19 +715,23 @@ __host__ __device__ inline uint64_t tiles_of(const Lattice &lat)
     return ((uint64_t)(lat.L / R) * lat.W + kBlock - 1) / kBlock;
 }
 
-// LDS of the compacting tiles: one list per model and group count, sharing
-// storage (a launch uses one of them at a time per tile).
-template <int CAP>
+// LDS of the compacting tiles, per wavefront: one list per model and group
+// count, sharing that wavefront's storage (a tile uses one of them).
+// Blume-Capel list slots per wavefront: 8 per row of the tile (about 6% of
+// the words are still undecided after eight planes).
+constexpr int bc_list_cap(int v) { return v == 4 ? 16 : 8 * variant_rows(v); }
+
+template <int V>
 union BcListUnion {
-    BcList<kBcGroupsDelta0, CAP> d0;
-    BcList<kBcGroups, CAP> gen;
+    BcList<kBcGroupsDelta0, bc_list_cap(V), variant_rows(V)> d0;
+    BcList<kBcGroups, bc_list_cap(V), variant_rows(V)> gen;
 };
 
-template <int CAP>
+template <int V>
 union AnyList {
-    WaveList<CAP> ising;
-    BcList<kBcGroupsDelta0, CAP> d0;
-    BcList<kBcGroups, CAP> gen;
+    WaveList<variant_list_cap(V)> ising;
+    BcList<kBcGroupsDelta0, bc_list_cap(V), variant_rows(V)> d0;
+    BcList<kBcGroups, bc_list_cap(V), variant_rows(V)> gen;
 };
 
 template <bool MEASURE, int V>
@@ -723,13 +742,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep_ising(Lattice lat, uint32_t c,
     unsigned long long e[kEmCounters] = {0, 0, 0, 0};
     const uint64_t ntiles = tiles_of<R>(lat);
     if constexpr (variant_compact(V)) {
-        __shared__ WaveList<variant_list_cap(V)> Q;
+        __shared__ WaveList<variant_list_cap(V)> Q[kWaves];
         if (lat.W % kBlock == 0) {
             for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-                ising_tile_compact<MEASURE, R, true>(lat, c, t, gt, tile, Q, e);
+                ising_tile_compact<MEASURE, R, true>(lat, c, t, gt, tile, Q[threadIdx.x >> 6], e);
         } else {
             for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-                ising_tile_compact<MEASURE, R, false>(lat, c, t, gt, tile, Q, e);
+                ising_tile_compact<MEASURE, R, false>(lat, c, t, gt, tile, Q[threadIdx.x >> 6], e);
         }
     } else if (lat.W % kBlock == 0) {
         for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
@@ -750,13 +769,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep_bc(Lattice lat, uint32_t c, ui
     unsigned long long e[kEmCounters] = {0, 0, 0, 0};
     const uint64_t ntiles = tiles_of<R>(lat);
     if constexpr (variant_compact(V)) {
-        __shared__ BcListUnion<variant_list_cap(V)> Q;
+        __shared__ BcListUnion<V> Q[kWaves];
         if (lat.bc_groups == kBcGroupsDelta0) {
             for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-                bc_tile_compact<MEASURE, R, kBcGroupsDelta0>(lat, c, t, gt, tile, Q.d0, e);
+                bc_tile_compact<MEASURE, R, kBcGroupsDelta0>(lat, c, t, gt, tile, Q[threadIdx.x >> 6].d0, e);
         } else {
             for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-                bc_tile_compact<MEASURE, R, kBcGroups>(lat, c, t, gt, tile, Q.gen, e);
+                bc_tile_compact<MEASURE, R, kBcGroups>(lat, c, t, gt, tile, Q[threadIdx.x >> 6].gen, e);
         }
     } else if (lat.bc_groups == kBcGroupsDelta0) {
         for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
@@ -779,7 +798,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica 
                                                              uint32_t stride, uint32_t step, uint32_t c)
 {
     constexpr int R = variant_rows(V);
-    __shared__ std::conditional_t<variant_compact(V), AnyList<variant_list_cap(V)>, int> Q;
+    __shared__ std::conditional_t<variant_compact(V), AnyList<V>, int> Q[kWaves];
     unsigned long long e[kEmCounters] = {0, 0, 0, 0};
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const uint32_t rid = tile_rep[tile];
@@ -790,13 +809,13 @@ __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica 
         if constexpr (variant_compact(V)) {
             if (rep.lat.model == kIsing) {
                 if (rep.lat.W % kBlock == 0)
-                    ising_tile_compact<false, R, true>(rep.lat, c, t, gt, local, Q.ising, e);
+                    ising_tile_compact<false, R, true>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].ising, e);
                 else
-                    ising_tile_compact<false, R, false>(rep.lat, c, t, gt, local, Q.ising, e);
+                    ising_tile_compact<false, R, false>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].ising, e);
             } else if (rep.lat.bc_groups == kBcGroupsDelta0)
-                bc_tile_compact<false, R, kBcGroupsDelta0>(rep.lat, c, t, gt, local, Q.d0, e);
+                bc_tile_compact<false, R, kBcGroupsDelta0>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].d0, e);
             else
-                bc_tile_compact<false, R, kBcGroups>(rep.lat, c, t, gt, local, Q.gen, e);
+                bc_tile_compact<false, R, kBcGroups>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].gen, e);
         } else if (rep.lat.model == kIsing) {
             if (rep.lat.W % kBlock == 0)
                 ising_tile_lazy<false, R, true>(rep.lat, c, t, gt, local, e);

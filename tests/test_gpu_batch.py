@@ -93,3 +93,34 @@ def test_batch_rejects_bad_descriptors(gpu):
     T2[0, 1] = -1.0
     with pytest.raises(gpu.SpinError):
         gpu.Batch(reps, T2)
+
+
+def test_many_tiles_per_block_mixed_models(gpu):
+    """Enough replicas that every block of the batched launch walks several
+    tiles of different models and group counts (Ising, Blume-Capel at
+    Delta = 0 and at Delta = 0.6).  Each wavefront's list storage must stay
+    its own while neighbouring wavefronts are at other tiles: every forced
+    strategy reproduces the solo runs."""
+    reps = []
+    for k in range(192):
+        kind = k % 3
+        reps.append(dict(model=0 if kind == 0 else 1, L=2048 if k % 2 else 1024, seed=workloads.seed_for(5000 + k),
+                         J=1.0, Delta=0.6 if kind == 2 else 0.0, schedule=k % 3))
+    n = 24
+    T = schedules(n)
+    T[0] = np.linspace(2.4, 2.2, n)   # keep every schedule finite and near the critical region
+    T[1] = np.linspace(1.9, 1.6, n)
+    T[2] = np.linspace(1.8, 1.5, n)
+    want = []
+    for rep in reps:
+        solo = gpu.Lattice(rep["model"], rep["L"], rep["seed"], rep["J"], rep["Delta"]).init_random()
+        solo.sweep(T[rep["schedule"]])
+        want.append(solo.spins())
+        solo.close()
+    for v in (1, 2, 4):
+        b = gpu.Batch(reps, T).init_random()
+        b.run(n, gpu.BATCH_VARIANT(v))
+        b.sync()
+        bad = [k for k in range(len(reps)) if not np.array_equal(b.spins(k), want[k])]
+        assert not bad, (v, bad[:10])
+        b.close()
