@@ -241,6 +241,14 @@ int spin_batch_sync(spin_batch *b);
 /* Borrow replica k's handle (measure, get/set spins); owned by the batch. */
 int spin_batch_replica(spin_batch *b, uint32_t k, spin_handle **out);
 
+/* Measure every replica's current state, as spin_measure on each replica's
+ * handle (paper Eqs. 2-3 and App. C): out[k] for replica k, Sx[k * n_r + q]
+ * and Sy[k * n_r + q] for separation r[q] (caller-owned host arrays of n and
+ * n * n_r entries; Sx, Sy may be NULL when n_r == 0).  Every r[q] must lie in
+ * 0 < r < L of every replica.  Synchronises the batch's stream. */
+int spin_batch_measure(spin_batch *b, const uint32_t *r, uint32_t n_r, spin_meas *out, int64_t *Sx,
+                       int64_t *Sy);
+
 /* Replica count, sweeps this batch has run, sweep strategy in use (-1 before
  * the first run) and tiles per half-sweep; any output may be NULL. */
 int spin_batch_info(const spin_batch *b, uint32_t *n_replicas, uint64_t *t, int *variant, uint64_t *tiles);

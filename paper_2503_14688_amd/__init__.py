@@ -56,7 +56,8 @@ EXPORTS = ["spin_lattice_bytes", "spin_create", "spin_init_random", "spin_sweep"
            "spin_get_t", "spin_threshold_table", "spin_schedule_fill", "spin_destroy",
            "spin_set_variant", "spin_get_variant", "spin_tune",
            "spin_last_error", "spin_batch_create", "spin_batch_init_random", "spin_batch_run",
-           "spin_batch_sync", "spin_batch_replica", "spin_batch_info", "spin_batch_destroy"]
+           "spin_batch_sync", "spin_batch_replica", "spin_batch_measure", "spin_batch_info",
+           "spin_batch_destroy"]
 
 
 def load_library():
@@ -104,6 +105,7 @@ def load_library():
         "spin_batch_run": (ctypes.c_int, [vp, ctypes.c_uint32, ctypes.c_uint32]),
         "spin_batch_sync": (ctypes.c_int, [vp]),
         "spin_batch_replica": (ctypes.c_int, [vp, ctypes.c_uint32, ctypes.POINTER(vp)]),
+        "spin_batch_measure": (ctypes.c_int, [vp, u32p, ctypes.c_uint32, ctypes.POINTER(spin_meas), i64p, i64p]),
         "spin_batch_info": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64),
                                            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_uint64)]),
         "spin_batch_destroy": (ctypes.c_int, [vp]),
@@ -258,6 +260,19 @@ def spin_batch_sync(b):
     _check(load_library().spin_batch_sync(b))
 
 
+def spin_batch_measure(b, n, r=()):
+    """Per-replica measurements: list of dicts as spin_measure returns."""
+    r = np.ascontiguousarray(r, dtype=np.uint32)
+    nr = r.shape[0]
+    out = (spin_meas * n)()
+    Sx = np.zeros((n, nr), dtype=np.int64)
+    Sy = np.zeros((n, nr), dtype=np.int64)
+    _check(load_library().spin_batch_measure(b, _ptr(r, ctypes.c_uint32), nr, out, _ptr(Sx, ctypes.c_int64),
+                                             _ptr(Sy, ctypes.c_int64)))
+    return [{"t": o.t, "sum_s": o.sum_s, "sum_s2": o.sum_s2, "bond": o.bond, "e": o.e, "m": o.m, "xi": o.xi,
+             "Sx": Sx[k], "Sy": Sy[k]} for k, o in enumerate(out)]
+
+
 def spin_batch_replica(b, k):
     h = ctypes.c_void_p()
     _check(load_library().spin_batch_replica(b, k, ctypes.byref(h)))
@@ -383,6 +398,9 @@ class Batch:
 
     def measure(self, k, r=()):
         return spin_measure(self.replica(k), r)
+
+    def measure_all(self, r=()):
+        return spin_batch_measure(self.b, len(self.reps), r)
 
     def info(self):
         return spin_batch_info(self.b)

@@ -384,6 +384,24 @@ int spin_batch_replica(spin_batch *b, uint32_t k, spin_handle **out)
     return 0;
 }
 
+int spin_batch_measure(spin_batch *b, const uint32_t *r, uint32_t n_r, spin_meas *out, int64_t *Sx, int64_t *Sy)
+{
+    if (!b || !out || (n_r && (!r || !Sx || !Sy)))
+        return fail(-EINVAL, "bad batch or NULL output");
+    for (size_t k = 0; k < b->reps.size(); ++k) {
+        const uint32_t L = b->reps[k]->L;
+        for (uint32_t q = 0; q < n_r; ++q)
+            if (r[q] == 0 || r[q] >= L)
+                return fail(-EINVAL, "separation %u outside 0 < r < L = %u of replica %zu", r[q], L, k);
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    for (size_t k = 0; k < b->reps.size(); ++k)
+        if (int rc = spin_measure(b->reps[k], r, n_r, out + k, n_r ? Sx + k * n_r : nullptr,
+                                  n_r ? Sy + k * n_r : nullptr, nullptr))
+            return rc;
+    return 0;
+}
+
 int spin_batch_info(const spin_batch *b, uint32_t *n_replicas, uint64_t *t, int *variant, uint64_t *tiles)
 {
     if (!b)

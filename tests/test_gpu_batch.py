@@ -124,3 +124,29 @@ def test_many_tiles_per_block_mixed_models(gpu):
         bad = [k for k in range(len(reps)) if not np.array_equal(b.spins(k), want[k])]
         assert not bad, (v, bad[:10])
         b.close()
+
+
+def test_batch_measure_all(gpu):
+    """spin_batch_measure: every replica's integers equal its own spin_measure
+    and, for a few replicas, the oracle's brute-force sums."""
+    reps = mixed_replicas()
+    T = schedules(12)
+    b = gpu.Batch(reps, T).init_random()
+    b.run(12)
+    r = [1, 2, 3, 5, 8, 13, 21, 32, 63]
+    got = b.measure_all(r)
+    assert len(got) == len(reps)
+    for k, rep in enumerate(reps):
+        one = b.measure(k, r)
+        for key in ("t", "sum_s", "sum_s2", "bond"):
+            assert got[k][key] == one[key], (k, key)
+        assert np.array_equal(got[k]["Sx"], one["Sx"]) and np.array_equal(got[k]["Sy"], one["Sy"])
+        assert got[k]["t"] == 12
+    for k in (0, len(reps) - 1):
+        s = b.spins(k)
+        want = oracle.measure(s, r)
+        assert got[k]["bond"] == want["bond"] and np.array_equal(got[k]["Sx"], want["Sx"])
+        assert np.array_equal(got[k]["Sy"], want["Sy"])
+    with pytest.raises(gpu.SpinError):
+        b.measure_all([64])  # not below L = 64 of the smallest replica
+    b.close()
