@@ -271,10 +271,6 @@ __device__ __forceinline__ void y_pairs(const uint32_t *ring, uint32_t slot0, in
                 cb[Q - Q0] += ok ? nb : 0u;
             }
         }
-        // keep at most three pairs' LDS rows in flight: the block's 16
-        // wavefronts leave each lane 128 registers
-        if constexpr ((Q - Q0) % 3 == 2)
-            __builtin_amdgcn_sched_barrier(0);
         y_pairs<MODEL, ALL_VALID, Q0, Q + 1>(ring, slot0, jr, x, j, L, RING, ca, cb);
     }
 }

@@ -60,6 +60,99 @@ __device__ __forceinline__ Block4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     return r;
 }
 
+// philox4x32_10 for a counter whose words 0, 2 and 3 are wave-uniform (row,
+// sweep index, stream tag) while word 1 (the word column) varies by lane.
+// The first rounds are written so that every value that is still uniform
+// stays in scalar registers (the compiler places plain C by divergence):
+// round 1 needs one vector operation, round 2 two, round 3 three, and only
+// from round 4 on is the whole state per lane.  Same result as philox4x32_10.
+__device__ __forceinline__ Block4 philox4x32_10_ru(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                   uint32_t k0, uint32_t k1)
+{
+    k0 = __builtin_amdgcn_readfirstlane(k0);
+    k1 = __builtin_amdgcn_readfirstlane(k1);
+    c0 = __builtin_amdgcn_readfirstlane(c0);
+    c2 = __builtin_amdgcn_readfirstlane(c2);
+    c3 = __builtin_amdgcn_readfirstlane(c3);
+    uint64_t p0, p1;
+    uint32_t n0, n2;
+    // round 1: words 0, 2, 3 uniform
+    p0 = (uint64_t)kPhiloxM0 * c0;
+    p1 = (uint64_t)kPhiloxM1 * c2;
+    n0 = ((uint32_t)(p1 >> 32) ^ k0) ^ c1;
+    n2 = ((uint32_t)(p0 >> 32) ^ k1) ^ c3;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+    // round 2: words 1, 2, 3 uniform
+    p0 = (uint64_t)kPhiloxM0 * c0;
+    p1 = (uint64_t)kPhiloxM1 * c2;
+    n0 = ((uint32_t)(p1 >> 32) ^ k0) ^ c1;
+    n2 = (uint32_t)(p0 >> 32) ^ (k1 ^ c3);
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+    // round 3: words 0 and 1 uniform
+    p0 = (uint64_t)kPhiloxM0 * c0;
+    p1 = (uint64_t)kPhiloxM1 * c2;
+    n0 = (uint32_t)(p1 >> 32) ^ (k0 ^ c1);
+    n2 = ((uint32_t)(p0 >> 32) ^ k1) ^ c3;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+    // round 4: word 3 uniform
+    p0 = (uint64_t)kPhiloxM0 * c0;
+    p1 = (uint64_t)kPhiloxM1 * c2;
+    n0 = xor3_key((uint32_t)(p1 >> 32), c1, k0);
+    n2 = (uint32_t)(p0 >> 32) ^ (k1 ^ c3);
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+#pragma unroll
+    for (int round = 4; round < 10; ++round) {
+        p0 = (uint64_t)kPhiloxM0 * c0;
+        p1 = (uint64_t)kPhiloxM1 * c2;
+        n0 = xor3_key((uint32_t)(p1 >> 32), c1, k0);
+        n2 = xor3_key((uint32_t)(p0 >> 32), c3, k1);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+    Block4 r;
+    r.v[0] = c0;
+    r.v[1] = c1;
+    r.v[2] = c2;
+    r.v[3] = c3;
+    return r;
+}
+
+// The Philox block of counter (row, word, t, tag): row-uniform form when
+// the caller knows the row is the same across the wavefront.
+template <bool ROW_UNIFORM>
+__device__ __forceinline__ Block4 philox_block(uint32_t row, uint32_t word, uint32_t t, uint32_t tag, uint32_t k0,
+                                               uint32_t k1)
+{
+    if constexpr (ROW_UNIFORM)
+        return philox4x32_10_ru(row, word, t, tag, k0, k1);
+    else
+        return philox4x32_10(row, word, t, tag, k0, k1);
+}
+
 // Stream purposes, placed in bits 16.. of counter word 3.
 constexpr uint32_t kPurposeInit = 0u;
 constexpr uint32_t kPurposeAccept = 1u;

@@ -243,14 +243,12 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
             const uint32_t never = (nev3 ? m3 : 0u) | (nev4 ? m4 : 0u);
             acc = ~(need[0] | need[1] | never);
             und = need[0] | need[1];
-            if (und != 0u) {
-                const Block4 b = philox4x32_10(i, w, t, stream_tag(kPurposeAccept, c, 0), k0, k1);
-                apply_block_2g(b, 0u, need, thr, und, acc);
-            }
-            if (und != 0u) {
-                const Block4 b = philox4x32_10(i, w, t, stream_tag(kPurposeAccept, c, 1), k0, k1);
-                apply_block_2g(b, 1u, need, thr, und, acc);
-            }
+            // blocks 0 and 1 for every word: the wavefront would run them
+            // anyway unless all 64 of its words were settled, which is rare
+            const Block4 b0 = philox_block<UNIFORM>(i, w, t, stream_tag(kPurposeAccept, c, 0), k0, k1);
+            apply_block_2g(b0, 0u, need, thr, und, acc);
+            const Block4 b1 = philox_block<UNIFORM>(i, w, t, stream_tag(kPurposeAccept, c, 1), k0, k1);
+            apply_block_2g(b1, 1u, need, thr, und, acc);
         }
         const unsigned long long bal = __ballot(und != 0u);
         bool listed = false;
