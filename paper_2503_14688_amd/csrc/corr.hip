@@ -7,7 +7,9 @@
 // shift of the partner plane (r even: same colour, m + r/2; r odd: other
 // colour, m + (r-1)/2 + ((i + c) & 1)), so with the set known at compile time
 // each pair costs one funnel shift, one XOR and one accumulating popcount.
-// The two halves of a block take 24 separations each.
+// The two halves of a block take 24 separations each.  When a row is a whole
+// number of 1024-word segments, k_corr_x_runs gives each lane a run of 8
+// consecutive words (nine LDS reads per separation instead of sixteen).
 //
 // Vertical (k_corr_y_ring): a block owns a 4-word (Ising) or 2-word
 // (Blume-Capel) column strip of both planes and walks down the lattice once,
@@ -124,6 +126,100 @@ __device__ __forceinline__ void x_group(int sg, const XTile<MODEL> &t, int tw, u
         x_segment<MODEL, P0, kXPer>(t, tw, ca, cb);
 }
 
+// Whole-segment form (rows that are a whole number of kTileW-word segments):
+// each lane walks a run of kXRun consecutive own words, so one separation
+// costs nine LDS reads for eight pairs instead of two per pair.  The staged
+// words of both planes sit side by side (E uint32 per word and plane) with
+// one spare uint32 after every 8 words: neighbouring lanes' runs start an
+// odd number of uint32 apart (distinct banks), and a run's partners stay
+// within the offset range of one LDS instruction.
+constexpr int kXRun = 8;
+
+template <int MODEL>
+struct XRunTile {
+    static constexpr int E = MODEL == kIsing ? 1 : 2;
+    __host__ __device__ static constexpr int idx(int e, int plane, int part)
+    {
+        return (e * 2 + plane) * E + part + (e >> 3);
+    }
+    uint32_t w[idx(kTileW + kHalo, 0, 0) + 1];
+};
+
+// acc + popcount(x) as one v_bcnt_u32_b32, kept in program order (the
+// compiler would otherwise re-associate a run's sum into a tree of partial
+// counts, all live at once).
+__device__ __forceinline__ uint32_t popc_acc(uint32_t x, uint32_t acc)
+{
+    uint32_t d;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(d) : "v"(x), "v"(acc));
+    return d;
+}
+
+// One lane's run of kXRun own words (plane C, row parity P, staged from
+// index base) against separations Q0 .. Q0 + kXPer - 1.  A separation is a
+// shift of s bits in plane tc, so the run's partners are the kXRun + 1 words
+// from s / 32 on, funnel-shifted by s % 32.
+template <int MODEL, int C, int P, int Q0, int Q>
+__device__ __forceinline__ void x_run_pairs(const XRunTile<MODEL> &t, int base, const uint32_t (&oz)[kXRun],
+                                            const uint32_t (&os)[kXRun], uint32_t (&ca)[kXPer],
+                                            uint32_t (&cb)[kXPer])
+{
+    if constexpr (Q < Q0 + kXPer) {
+        {
+            constexpr uint32_t r = sparse_r(Q);
+            constexpr int tc = C ^ (int)(r & 1u);
+            constexpr uint32_t s = (r >> 1) + ((r & 1u) & (uint32_t)P);
+            constexpr int qw = (int)(s >> 5);
+            constexpr uint32_t rr = s & 31u;
+            constexpr int E = XRunTile<MODEL>::E;
+            uint32_t xz[kXRun + 1], xs[kXRun + 1];
+#pragma unroll
+            for (int m = 0; m <= kXRun; ++m) {
+                // the run's first word is a multiple of 8: idx(e0 + c) = base + idx(c)
+                xs[m] = t.w[base + XRunTile<MODEL>::idx(qw + m, tc, E - 1)];
+                xz[m] = MODEL == kIsing ? ~0u : t.w[base + XRunTile<MODEL>::idx(qw + m, tc, 0)];
+            }
+            uint32_t na = ca[Q - Q0], nb = cb[Q - Q0];
+#pragma unroll
+            for (int j = 0; j < kXRun; ++j) {
+                const uint32_t bs = rr ? __builtin_amdgcn_alignbit(xs[j + 1], xs[j], rr) : xs[j];
+                if constexpr (MODEL == kIsing) {
+                    nb = popc_acc(os[j] ^ bs, nb);
+                } else {
+                    const uint32_t bz = rr ? __builtin_amdgcn_alignbit(xz[j + 1], xz[j], rr) : xz[j];
+                    const uint32_t both = oz[j] & bz;
+                    na = popc_acc(both, na);
+                    nb = popc_acc(both & (os[j] ^ bs), nb);
+                }
+            }
+            ca[Q - Q0] = na;
+            cb[Q - Q0] = nb;
+        }
+        __builtin_amdgcn_sched_barrier(0);  // one separation's partners at a time
+        x_run_pairs<MODEL, C, P, Q0, Q + 1>(t, base, oz, os, ca, cb);
+    }
+}
+
+template <int MODEL, int P0, int Q0>
+__device__ __forceinline__ void x_runs(const XRunTile<MODEL> &t, uint32_t (&ca)[kXPer], uint32_t (&cb)[kXPer])
+{
+    constexpr int E = XRunTile<MODEL>::E;
+    const int base = XRunTile<MODEL>::idx((int)(threadIdx.x % (kBlock / kXGroups)) * kXRun, 0, 0);
+#pragma unroll
+    for (int C = 0; C < 2; ++C) {
+        uint32_t oz[kXRun], os[kXRun];
+#pragma unroll
+        for (int j = 0; j < kXRun; ++j) {
+            os[j] = t.w[base + XRunTile<MODEL>::idx(j, C, E - 1)];
+            oz[j] = MODEL == kIsing ? ~0u : t.w[base + XRunTile<MODEL>::idx(j, C, 0)];
+        }
+        if (C == 0)
+            x_run_pairs<MODEL, 0, P0, Q0, Q0>(t, base, oz, os, ca, cb);
+        else
+            x_run_pairs<MODEL, 1, P0 ^ 1, Q0, Q0>(t, base, oz, os, ca, cb);
+    }
+}
+
 // Block sums of per-group counters: each wavefront adds its group's counters
 // (one LDS atomic per counter and wavefront), then one atomic per counter and
 // block to HBM.  acc[2q] takes ca, acc[2q + 1] takes cb.
@@ -195,6 +291,51 @@ __global__ __launch_bounds__(kBlock) void k_corr_x_sparse(Lattice lat, int n_r, 
             x_group<MODEL, 1>(sg, t, tw, ca, cb);
         else
             x_group<MODEL, 0>(sg, t, tw, ca, cb);
+    }
+    flush_groups<MODEL != kIsing, kXPer>(ca, cb, sg, n_r, acc);
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(kBlock) void k_corr_x_runs(Lattice lat, int n_r, unsigned long long *acc)
+{
+    __shared__ XRunTile<MODEL> t;
+    constexpr int E = XRunTile<MODEL>::E;
+    static_assert(kXRun * (kBlock / kXGroups) == kTileW, "a group's runs cover the segment");
+    const uint32_t L = lat.L, W = lat.W;
+    const uint32_t tiles_per_row = W / kTileW;  // W is a multiple of kTileW
+    const uint64_t ntiles = (uint64_t)L * tiles_per_row;
+    const int sg = (int)(threadIdx.x / (kBlock / kXGroups));  // separation group (wave-uniform)
+    uint32_t ca[kXPer], cb[kXPer];
+#pragma unroll
+    for (int q = 0; q < kXPer; ++q) {
+        ca[q] = 0;
+        cb[q] = 0;
+    }
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t i = (uint32_t)(tile / tiles_per_row);
+        const uint32_t w0 = (uint32_t)(tile - (uint64_t)i * tiles_per_row) * kTileW;
+        __syncthreads();
+        for (int k = threadIdx.x; k < (kTileW + kHalo) * E; k += kBlock) {
+            const int e = k / E, part = k - e * E;
+            uint32_t wk = w0 + (uint32_t)e;
+            if (wk >= W)
+                wk -= W;  // W >= kTileW > kHalo
+            const size_t off = ((size_t)i * W + wk) * E + part;
+            t.w[XRunTile<MODEL>::idx(e, 0, part)] = lat.planes[off];
+            t.w[XRunTile<MODEL>::idx(e, 1, part)] = lat.planes[lat.plane_u32 + off];
+        }
+        __syncthreads();
+        if (i & 1u) {
+            if (sg == 0)
+                x_runs<MODEL, 1, 0>(t, ca, cb);
+            else
+                x_runs<MODEL, 1, kXPer>(t, ca, cb);
+        } else {
+            if (sg == 0)
+                x_runs<MODEL, 0, 0>(t, ca, cb);
+            else
+                x_runs<MODEL, 0, kXPer>(t, ca, cb);
+        }
     }
     flush_groups<MODEL != kIsing, kXPer>(ca, cb, sg, n_r, acc);
 }
@@ -402,10 +543,18 @@ hipError_t launch_corr_sparse(const Lattice &lat, bool vertical, int n_r, unsign
     if (!vertical) {
         const uint64_t tiles = (uint64_t)lat.L * ((lat.W + kTileW - 1) / kTileW);
         const dim3 grid(corr_grid(tiles, 2048)), block(kBlock);
-        if (lat.model == kIsing)
-            hipLaunchKernelGGL(k_corr_x_sparse<kIsing>, grid, block, 0, st, lat, n_r, acc);
-        else
-            hipLaunchKernelGGL(k_corr_x_sparse<kBlumeCapel>, grid, block, 0, st, lat, n_r, acc);
+        const bool runs = lat.W % kTileW == 0;
+        if (lat.model == kIsing) {
+            if (runs)
+                hipLaunchKernelGGL(k_corr_x_runs<kIsing>, grid, block, 0, st, lat, n_r, acc);
+            else
+                hipLaunchKernelGGL(k_corr_x_sparse<kIsing>, grid, block, 0, st, lat, n_r, acc);
+        } else {
+            if (runs)
+                hipLaunchKernelGGL(k_corr_x_runs<kBlumeCapel>, grid, block, 0, st, lat, n_r, acc);
+            else
+                hipLaunchKernelGGL(k_corr_x_sparse<kBlumeCapel>, grid, block, 0, st, lat, n_r, acc);
+        }
         return hipGetLastError();
     }
     const uint32_t r_max = sparse_r(n_r - 1);
