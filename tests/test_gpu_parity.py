@@ -205,6 +205,23 @@ def test_sparse_and_generic_correlation_kernels_agree(gpu, model, L):
     lat.close()
 
 
+@pytest.mark.parametrize("model,L", [(0, 65536), (0, 131072), (1, 65536)])
+def test_whole_segment_correlation_kernel(gpu, model, L):
+    """Rows of whole 1024-word segments take the run-per-lane horizontal
+    kernel (one segment per row at L = 65536, where the halo wraps to the
+    row start; two at L = 131072, where it runs into the next segment).  It
+    must match the generic per-separation kernels on the full sparse set."""
+    lat = make(gpu, model, L, 29)
+    lat.sweep(np.full(2, 2.2 if model == 0 else 1.6))
+    r_fast = workloads.r_sparse(L)
+    r_slow = np.append(r_fast, np.uint32(r_fast[-1] + 1))
+    a, b = lat.measure(r_fast), lat.measure(r_slow)
+    n = len(r_fast)
+    assert np.array_equal(a["Sx"], b["Sx"][:n]) and np.array_equal(a["Sy"], b["Sy"][:n])
+    assert a["bond"] == b["bond"]
+    lat.close()
+
+
 @pytest.mark.parametrize("model", [0, 1])
 def test_sweep_strategies_agree(gpu, model):
     """All sweep strategies (rows per thread, per-word or compacting lazy
