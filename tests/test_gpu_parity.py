@@ -296,7 +296,9 @@ def test_blume_capel_L4096_check_run(gpu):
 
 def sampled_full_size(gpu, model, L, T, n_sweeps, seed, windows, J=1.0, Delta=0.0):
     import torch
-    lat = make(gpu, model, L, seed, J, Delta)
+    lat = gpu.Lattice(model, L, seed, J, Delta)
+    lat.variant = lat.tune(T)  # the launch configuration the benchmark times
+    lat.init_random()
     lat.sweep(np.full(n_sweeps, T), fuse_measure=True)
     k = 2 * n_sweeps
     for (i0, j0, size) in windows:
@@ -315,6 +317,11 @@ def sampled_full_size(gpu, model, L, T, n_sweeps, seed, windows, J=1.0, Delta=0.
     assert fused["bond"] == again["bond"] == int(fused["Sx"][0] + fused["Sy"][0])
     assert fused["sum_s"] == again["sum_s"] and fused["sum_s2"] == again["sum_s2"]
     assert abs(fused["sum_s"]) <= fused["sum_s2"] <= L * L
+    # C(r) on the full sparse set: the fast kernels against the generic ones
+    r_fast = workloads.r_sparse(L)
+    r_slow = np.append(r_fast, np.uint32(r_fast[-1] + 1))
+    a, b = lat.measure(r_fast), lat.measure(r_slow)
+    assert np.array_equal(a["Sx"], b["Sx"][:len(r_fast)]) and np.array_equal(a["Sy"], b["Sy"][:len(r_fast)])
     lat.close()
     del lat
     torch.cuda.empty_cache()
