@@ -13,10 +13,13 @@
 //
 // Vertical (k_corr_y_ring): a block owns a 4-word (Ising) or 2-word
 // (Blume-Capel) column strip of both planes and walks down the lattice once,
-// keeping the last r_max + 256 rows in an LDS ring; each new row meets its
+// keeping the last r_max + 512 rows in an LDS ring; each new row meets its
 // 48 partners above it in the ring (four threads per row, twelve
 // separations each), so the lattice is read from HBM about once for all
-// separations.
+// separations.  The ring stores 16-row blocks plane by plane so that the
+// 16-byte LDS loads of neighbouring lanes never share a bank, the four
+// separation groups take turns at loading the rows four chunks ahead, and
+// one barrier per 256-row chunk suffices.
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -342,13 +345,28 @@ __global__ __launch_bounds__(kBlock) void k_corr_x_runs(Lattice lat, int n_r, un
 
 // -------------------------------------------------------------- vertical --
 
-// A ring row is 8 uint32 (32 bytes): Ising words [w0, w0 + 4) of plane 0 then
-// plane 1; Blume-Capel (Z, S) of words [w0, w0 + 2) of plane 0 then plane 1.
-// Thread jr of a block owns ring row j0 + jr of every chunk: it reads its own
-// row once and, for each separation, the row r above it with two 16-byte
-// LDS loads, pairing all 8 words at once.
+// A ring row is 8 uint32 (32 bytes): a 16-byte half of plane 0 (Ising words
+// [w0, w0 + 4), Blume-Capel (Z, S) of words [w0, w0 + 2)) and the same half
+// of plane 1.  Thread jr of a block owns ring row j0 + jr of every chunk: it
+// reads its own row once and, for each separation, the row r above it with
+// two 16-byte LDS loads, pairing all 8 words at once.
 constexpr int kRingCols = 8;
 constexpr int kChunk = kBlock;  // ring rows per chunk, one per thread
+static_assert(kChunk % 16 == 0, "chunks start on a 16-row block of the ring");
+
+// Rows are stored in blocks of 16: the plane-0 halves of the block's 16 rows
+// (256 bytes), then their plane-1 halves.  Consecutive lanes read consecutive
+// rows, so one 16-byte load of 16 neighbouring lanes covers 256 contiguous
+// bytes modulo the block boundary: every bank once.  (With whole 32-byte
+// rows side by side, lanes 16 bytes apart in bank space would collide two by
+// two, which halves the LDS read rate.)  A row's plane-1 half is always 256
+// bytes past its plane-0 half: one immediate offset.
+constexpr uint32_t kHalfStep = 64;  // uint32 from a row's plane-0 half to its plane-1 half
+
+__host__ __device__ constexpr uint32_t ring_index(uint32_t s)
+{
+    return (s + (s & ~15u)) * 4u;
+}
 
 template <int MODEL>
 struct YShape {
@@ -359,14 +377,20 @@ struct Row8 {
     uint32_t v[8];
 };
 
-__device__ __forceinline__ Row8 lds_row(const uint32_t *ring, uint32_t slot)
+__device__ __forceinline__ Row8 lds_row(const uint32_t *p)
 {
-    const uint4 *p = reinterpret_cast<const uint4 *>(ring + (size_t)slot * kRingCols);
-    const uint4 a = p[0], b = p[1];
+    const uint4 a = *reinterpret_cast<const uint4 *>(p);
+    const uint4 b = *reinterpret_cast<const uint4 *>(p + kHalfStep);
     Row8 r;
     r.v[0] = a.x; r.v[1] = a.y; r.v[2] = a.z; r.v[3] = a.w;
     r.v[4] = b.x; r.v[5] = b.y; r.v[6] = b.z; r.v[7] = b.w;
     return r;
+}
+
+__device__ __forceinline__ void lds_store_row(uint32_t *p, const uint4 &h0, const uint4 &h1)
+{
+    *reinterpret_cast<uint4 *>(p) = h0;
+    *reinterpret_cast<uint4 *>(p + kHalfStep) = h1;
 }
 
 // Separation groups of the vertical kernel: a block has kYGroups threads per
@@ -377,80 +401,95 @@ constexpr int kYGroups = 4;
 constexpr int kYPer = kSparseN / kYGroups;
 constexpr int kYThreads = kChunk * kYGroups;
 
-// Pairs of the thread's partner row x (row j) with the base row j - r for the
-// separations Q0 .. Q0 + kYPer - 1.  Base plane c, partner plane c ^ (r & 1),
-// same words.
-template <int MODEL, bool ALL_VALID, int Q0, int Q>
-__device__ __forceinline__ void y_pairs(const uint32_t *ring, uint32_t slot0, int jr, const Row8 &x, int64_t j,
-                                        uint32_t L, uint32_t RING, uint32_t (&ca)[kYPer], uint32_t (&cb)[kYPer])
+// Row r above row j0 + jr of the chunk at ring slot slot0.  Its slot is
+// base + jr, base = (slot0 - r) mod RING the same for the whole block (rows
+// RING .. RING + kChunk - 1 mirror rows 0 .. kChunk - 1, so base + jr needs
+// no second wrap).  slot0 and RING are multiples of 16, so base % 16 = bl is
+// fixed by r, and ring_index(base + jr) = ring_index(bl + jr) + 8 (base - bl):
+// a per-lane part that is the same for every chunk plus a scalar, one vector
+// add per pair.
+template <uint32_t r>
+__device__ __forceinline__ Row8 y_row(const uint32_t *ring, int jr, uint32_t slot0, uint32_t RING)
+{
+    constexpr uint32_t bl = (16u - (r & 15u)) & 15u;
+    uint32_t base = slot0 + RING - (r % RING);
+    if (base >= RING)
+        base -= RING;
+    base = __builtin_amdgcn_readfirstlane(base);
+    return lds_row(ring + ring_index(bl + (uint32_t)jr) + (base - bl) * kRingCols);
+}
+
+// Counts of one pair, added to the running counters (b: base row j - r,
+// x: partner row j; base plane c pairs with partner plane c ^ (r & 1), same
+// words): Ising nb += #antiparallel; Blume-Capel na += #both nonzero,
+// nb += #both nonzero and opposite.
+template <int MODEL, int Q>
+__device__ __forceinline__ void y_count(const Row8 &b, const Row8 &x, uint32_t &na, uint32_t &nb)
+{
+    constexpr uint32_t r = sparse_r(Q);
+    constexpr int flip = (r & 1u) ? 4 : 0;  // partner column of base column k: k ^ flip
+    if constexpr (MODEL == kIsing) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            nb = popc_acc(b.v[k] ^ x.v[k ^ flip], nb);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; k += 2) {
+            const uint32_t both = b.v[k] & x.v[k ^ flip];
+            na = popc_acc(both, na);
+            nb = popc_acc(both & (b.v[k + 1] ^ x.v[(k ^ flip) + 1]), nb);
+        }
+    }
+}
+
+// Chunks whose pairs are all inside the lattice: the counters themselves
+// accumulate.
+template <int MODEL, int Q0, int Q>
+__device__ __forceinline__ void y_pairs_inner(const uint32_t *ring, int jr, uint32_t slot0, uint32_t RING,
+                                              const Row8 &x, uint32_t (&ca)[kYPer], uint32_t (&cb)[kYPer])
 {
     if constexpr (Q < Q0 + kYPer) {
-        {
-            constexpr uint32_t r = sparse_r(Q);
-            constexpr int flip = (r & 1u) ? 4 : 0;  // partner column of base column k: k ^ flip
-            uint32_t base = slot0 + RING - (r % RING);
-            if (base >= RING)
-                base -= RING;
-            const Row8 b = lds_row(ring, base + (uint32_t)jr);  // mirrored past RING
-            const int64_t i = j - (int64_t)r;
-            const bool ok = ALL_VALID || (i >= 0 && i < (int64_t)L);
-            if constexpr (MODEL == kIsing) {
-                uint32_t n = 0;
-#pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    n += __popc(b.v[k] ^ x.v[k ^ flip]);
-                cb[Q - Q0] += ok ? n : 0u;
-            } else {
-                uint32_t na = 0, nb = 0;
-#pragma unroll
-                for (int k = 0; k < 8; k += 2) {
-                    const uint32_t both = b.v[k] & x.v[k ^ flip];
-                    na += __popc(both);
-                    nb += __popc(both & (b.v[k + 1] ^ x.v[(k ^ flip) + 1]));
-                }
-                ca[Q - Q0] += ok ? na : 0u;
-                cb[Q - Q0] += ok ? nb : 0u;
-            }
-        }
-        y_pairs<MODEL, ALL_VALID, Q0, Q + 1>(ring, slot0, jr, x, j, L, RING, ca, cb);
+        const Row8 b = y_row<sparse_r(Q)>(ring, jr, slot0, RING);
+        y_count<MODEL, Q>(b, x, ca[Q - Q0], cb[Q - Q0]);
+        y_pairs_inner<MODEL, Q0, Q + 1>(ring, jr, slot0, RING, x, ca, cb);
     }
 }
 
-template <int MODEL, bool ALL_VALID>
-__device__ __forceinline__ void y_group(int sg, const uint32_t *ring, uint32_t slot0, int jr, const Row8 &x,
-                                        int64_t j, uint32_t L, uint32_t RING, uint32_t (&ca)[kYPer],
-                                        uint32_t (&cb)[kYPer])
+// Chunks at the top and bottom of the walk: a pair counts only when both
+// rows are lattice rows (j - r >= 0 and j < L).
+template <int MODEL, int Q0, int Q>
+__device__ __forceinline__ void y_pairs_edge(const uint32_t *ring, int jr, uint32_t slot0, uint32_t RING,
+                                             const Row8 &x, int64_t j, uint32_t L, uint32_t (&ca)[kYPer],
+                                             uint32_t (&cb)[kYPer])
 {
-    static_assert(kYGroups == 4, "one case per group");
-    switch (sg) {  // wave-uniform
-    case 0: y_pairs<MODEL, ALL_VALID, 0, 0>(ring, slot0, jr, x, j, L, RING, ca, cb); break;
-    case 1: y_pairs<MODEL, ALL_VALID, kYPer, kYPer>(ring, slot0, jr, x, j, L, RING, ca, cb); break;
-    case 2: y_pairs<MODEL, ALL_VALID, 2 * kYPer, 2 * kYPer>(ring, slot0, jr, x, j, L, RING, ca, cb); break;
-    default: y_pairs<MODEL, ALL_VALID, 3 * kYPer, 3 * kYPer>(ring, slot0, jr, x, j, L, RING, ca, cb); break;
+    if constexpr (Q < Q0 + kYPer) {
+        constexpr uint32_t r = sparse_r(Q);
+        const Row8 b = y_row<r>(ring, jr, slot0, RING);
+        uint32_t na = 0, nb = 0;
+        y_count<MODEL, Q>(b, x, na, nb);
+        const int64_t i = j - (int64_t)r;
+        const bool ok = i >= 0 && i < (int64_t)L;
+        ca[Q - Q0] += ok ? na : 0u;
+        cb[Q - Q0] += ok ? nb : 0u;
+        y_pairs_edge<MODEL, Q0, Q + 1>(ring, jr, slot0, RING, x, j, L, ca, cb);
     }
 }
 
-template <int MODEL>
-__global__ __launch_bounds__(kYThreads) void k_corr_y_ring(Lattice lat, int n_r, uint32_t RING,
-                                                           unsigned long long *acc)
+// One separation group's walk over the block's strips (Q0: the group's first
+// separation).  Each group has its own copy of the loop, so the per-lane
+// address parts of its separations stay in registers for the whole walk.
+template <int MODEL, int Q0>
+__device__ __forceinline__ void y_walk(const Lattice &lat, int n_r, uint32_t RING, uint32_t *ring, int jr,
+                                       uint32_t (&ca)[kYPer], uint32_t (&cb)[kYPer])
 {
-    extern __shared__ uint32_t ring[];  // (RING + kChunk) rows of kRingCols words
     constexpr int SW = YShape<MODEL>::SW;
     constexpr int E = MODEL == kIsing ? 1 : 2;
+    constexpr int sg = Q0 / kYPer;  // this group
     const uint32_t L = lat.L, W = lat.W;
     const uint32_t strips = W / SW;
     const uint32_t r_max = sparse_r(n_r - 1);
     const int64_t rows_total = (int64_t)L + r_max;  // partner rows j = 0 .. L + r_max - 1
     const int64_t nchunks = (rows_total + kChunk - 1) / kChunk;
-    const int jr = threadIdx.x % kChunk;  // ring row of the chunk
-    const int sg = threadIdx.x / kChunk;  // separation group (wave-uniform)
-    const bool loader = sg == 0;          // the first kChunk threads move rows into the ring
-    uint32_t ca[kYPer], cb[kYPer];
-#pragma unroll
-    for (int q = 0; q < kYPer; ++q) {
-        ca[q] = 0;
-        cb[q] = 0;
-    }
     // A strip row is 16 bytes of each plane, an eighth of a 128-byte line.
     // Blocks are dealt round-robin to the eight XCDs (block b on XCD b % 8),
     // so when the strips are a whole number of lines and the grid a multiple
@@ -473,37 +512,76 @@ __global__ __launch_bounds__(kYThreads) void k_corr_y_ring(Lattice lat, int n_r,
             p0 = *reinterpret_cast<const uint4 *>(lat.planes + off);
             p1 = *reinterpret_cast<const uint4 *>(lat.planes + lat.plane_u32 + off);
         };
+        // The groups take turns at loading: group g holds chunk ch in registers
+        // for ch % kYGroups == g, read kYGroups chunks before it is stored.
         uint4 n0{}, n1{};
         __syncthreads();
-        if (loader)
-            load_row(jr, n0, n1);
+        if (sg < nchunks)
+            load_row((int64_t)sg * kChunk + jr, n0, n1);
+        uint32_t slot0 = 0;  // ring slot of the chunk's first row: j0 mod RING
+        int turn = 0;        // ch % kYGroups
         for (int64_t ch = 0; ch < nchunks; ++ch) {
             const int64_t j0 = ch * kChunk;
-            const uint32_t slot0 = (uint32_t)(j0 % (int64_t)RING);  // multiple of kChunk
+            const bool loader = turn == sg;  // wave-uniform
             if (loader) {
-                uint4 *dst = reinterpret_cast<uint4 *>(ring + (size_t)(slot0 + jr) * kRingCols);
-                dst[0] = n0;
-                dst[1] = n1;
-                if (slot0 == 0) {
-                    uint4 *mir = reinterpret_cast<uint4 *>(ring + (size_t)(RING + jr) * kRingCols);
-                    mir[0] = n0;
-                    mir[1] = n1;
-                }
+                lds_store_row(ring + ring_index(slot0 + (uint32_t)jr), n0, n1);
+                if (slot0 == 0)
+                    lds_store_row(ring + ring_index(RING + (uint32_t)jr), n0, n1);
             }
             __syncthreads();
-            if (loader && ch + 1 < nchunks)
-                load_row(j0 + kChunk + jr, n0, n1);
-            const int64_t j = j0 + jr;
-            const Row8 x = lds_row(ring, slot0 + (uint32_t)jr);
+            if (loader && ch + kYGroups < nchunks)
+                load_row(j0 + kYGroups * kChunk + jr, n0, n1);
+            turn = turn + 1 == kYGroups ? 0 : turn + 1;
+            const Row8 x = lds_row(ring + ring_index(slot0 + (uint32_t)jr));
             // every pair of the chunk is valid when j0 - r >= 0 for the largest r
             // of the set and j0 + kChunk - 1 - r < L for r = 1
-            const bool all_valid = j0 >= (int64_t)sparse_r(kSparseN - 1) && j0 + kChunk - 1 < (int64_t)L + 1;
-            if (all_valid)
-                y_group<MODEL, true>(sg, ring, slot0, jr, x, j, L, RING, ca, cb);
+            if (j0 >= (int64_t)sparse_r(kSparseN - 1) && j0 + kChunk - 1 < (int64_t)L + 1)
+                y_pairs_inner<MODEL, Q0, Q0>(ring, jr, slot0, RING, x, ca, cb);
             else
-                y_group<MODEL, false>(sg, ring, slot0, jr, x, j, L, RING, ca, cb);
-            __syncthreads();
+                y_pairs_edge<MODEL, Q0, Q0>(ring, jr, slot0, RING, x, j0 + jr, L, ca, cb);
+            // No barrier here: a wave that finishes early may store the next
+            // chunk while others still pair this one.  The next chunk's slots
+            // hold rows at least RING - 2 kChunk + 1 > r_max above this
+            // chunk's first row (RING >= r_max + 2 kChunk), which no pair of
+            // this chunk reads, and this chunk never reads the mirror rows
+            // that a store at slot 0 rewrites (it sits at slot RING - kChunk
+            // then, and its partner slots do not wrap).
+            slot0 += kChunk;
+            if (slot0 == RING)
+                slot0 = 0;
         }
+    }
+}
+
+// Ring rows (a multiple of kChunk): room for the r_max rows above a chunk,
+// the chunk itself and the next chunk, which an early wave may store while
+// the others still pair this one.  With r_max = 4096 the ring and its
+// kChunk mirror rows take 152 KiB of LDS.
+static uint32_t y_ring_rows(int n_r)
+{
+    const uint32_t r_max = sparse_r(n_r - 1);
+    return (r_max + 2u * kChunk + kChunk - 1u) / kChunk * kChunk;
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(kYThreads) void k_corr_y_ring(Lattice lat, int n_r, uint32_t RING,
+                                                           unsigned long long *acc)
+{
+    extern __shared__ uint32_t ring[];  // (RING + kChunk) rows of kRingCols words
+    const int jr = threadIdx.x % kChunk;  // ring row of the chunk
+    const int sg = threadIdx.x / kChunk;  // separation group (wave-uniform)
+    uint32_t ca[kYPer], cb[kYPer];
+#pragma unroll
+    for (int q = 0; q < kYPer; ++q) {
+        ca[q] = 0;
+        cb[q] = 0;
+    }
+    static_assert(kYGroups == 4, "one case per group");
+    switch (sg) {  // every group passes the same barriers the same number of times
+    case 0: y_walk<MODEL, 0>(lat, n_r, RING, ring, jr, ca, cb); break;
+    case 1: y_walk<MODEL, kYPer>(lat, n_r, RING, ring, jr, ca, cb); break;
+    case 2: y_walk<MODEL, 2 * kYPer>(lat, n_r, RING, ring, jr, ca, cb); break;
+    default: y_walk<MODEL, 3 * kYPer>(lat, n_r, RING, ring, jr, ca, cb); break;
     }
     flush_groups<MODEL != kIsing, kYPer>(ca, cb, sg, n_r, acc);
 }
@@ -557,8 +635,7 @@ hipError_t launch_corr_sparse(const Lattice &lat, bool vertical, int n_r, unsign
         }
         return hipGetLastError();
     }
-    const uint32_t r_max = sparse_r(n_r - 1);
-    const uint32_t RING = (r_max + kChunk + kChunk - 1) / kChunk * kChunk;
+    const uint32_t RING = y_ring_rows(n_r);
     const size_t lds = (size_t)(RING + kChunk) * kRingCols * sizeof(uint32_t);
     if (lat.model == kIsing) {
         const dim3 grid(corr_grid(lat.W / YShape<kIsing>::SW, 256)), block(kYThreads);
@@ -574,12 +651,5 @@ hipError_t launch_corr_sparse(const Lattice &lat, bool vertical, int n_r, unsign
     return hipGetLastError();
 }
 
-size_t corr_sparse_y_lds(const Lattice &lat, int n_r)
-{
-    (void)lat;
-    const uint32_t r_max = sparse_r(n_r - 1);
-    const uint32_t RING = (r_max + kChunk + kChunk - 1) / kChunk * kChunk;
-    return (size_t)(RING + kChunk) * kRingCols * sizeof(uint32_t);
-}
 
 } // namespace spin

@@ -86,7 +86,6 @@ hipError_t launch_corr(const Lattice &lat, bool vertical, const uint32_t *r, int
 bool sparse_prefix(const uint32_t *r, int n_r);
 bool corr_sparse_x_ok(const Lattice &lat, const uint32_t *r, int n_r);
 bool corr_sparse_y_ok(const Lattice &lat, const uint32_t *r, int n_r);
-size_t corr_sparse_y_lds(const Lattice &lat, int n_r);
 hipError_t launch_corr_sparse(const Lattice &lat, bool vertical, int n_r, unsigned long long *acc,
                               hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t st);
