@@ -175,6 +175,43 @@ def run_serving(args, saturated_flips_per_ns):
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in stats.items()}
 
 
+def run_protocol2(args):
+    """The paper's pre-cooling protocol at L = 2^16: one run at T1 locates
+    t_switch(f) for every f from the measured xi(t), then the three two-step
+    runs (same seed, so the same trajectory up to each switch) go to t_max
+    as one batch.  value: all attempted flips of both phases / wall time."""
+    import torch
+    import paper_2503_14688_amd as spin
+    from paper_2503_14688_amd import protocols, workloads
+    wl = workloads.PROTOCOL2_ISING
+    L, seed, T1, T2, fs = wl["L"], wl["seed"], wl["T1"], wl["T2"], wl["f"]
+    r = workloads.r_sparse(L)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    lat = spin.Lattice(wl["model"], L, seed).init_random()
+    lat.variant = lat.tune(T1)
+    t_sw, curve = protocols.switch_times(lat, T1, fs, wl["xi_eq"], r, wl["t_limit"])
+    sweeps_a = lat.t
+    lat.close()
+    del lat
+    if any(t_sw[f] is None for f in fs):
+        raise RuntimeError(f"xi did not reach f xi_eq within {wl['t_limit']} sweeps at T1: {t_sw}")
+    tsw = [t_sw[f] for f in fs]
+    times = protocols.log_times(wl["t_max"], 4)
+    runs = protocols.two_step_batch(wl["model"], L, [seed] * len(fs), T1, T2, tsw, times, r)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    flips = float(L) * L * (sweeps_a + len(fs) * wl["t_max"])
+    log(f"protocol 2: t_switch {tsw} (paper {list(wl['t_switch_paper'])}), {flips / wall / 1e9:.1f} flips/ns")
+    return {"workload": wl["name"], "T1": T1, "T2": T2, "xi_eq_T2": wl["xi_eq"], "f": list(fs),
+            "t_switch": tsw, "t_switch_paper": list(wl["t_switch_paper"]),
+            "xi_at_T1": {str(m["t"]): round(m["xi"], 3) for m in curve if m["t"] in (256, 1024, 4096)},
+            "t_max": wl["t_max"], "sweeps_at_T1": sweeps_a, "wall_s": round(wall, 3),
+            "flips_per_ns": round(flips / wall / 1e9, 2),
+            "E_at_t_max": [round(run[-1]["e"], 6) for run in runs],
+            "xi_at_t_max": [round(run[-1]["xi"], 2) for run in runs]}
+
+
 def run(args):
     import torch
     import paper_2503_14688_amd as spin
@@ -251,6 +288,8 @@ def run(args):
     if not args.skip_serving:
         sat = out["batched"]["flips_per_ns"] if "batched" in out else out["sweep_only_flips_per_ns"]
         out["serving"] = run_serving(args, sat)
+    if not args.skip_protocol2:
+        out["protocol2"] = run_protocol2(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
     return out
@@ -280,6 +319,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
+    ap.add_argument("--skip-protocol2", action="store_true")
     ap.add_argument("--replicas", type=int, default=512)
     ap.add_argument("--batch-sweeps", type=int, default=4096)
     ap.add_argument("--compare-sweeps", type=int, default=256)

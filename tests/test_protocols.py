@@ -1,0 +1,114 @@
+"""Host logic of the thermal-protocol drivers on the CPU.
+
+The oracle stands in for the device behind the lattice interface (sweep,
+measure, t), so the drivers' choice of temperatures and measurement times is
+checked against plain oracle runs of the same schedules; the crossing-time
+rule is pinned by a power law, for which interpolation in (log t, log xi) is
+exact."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2503_14688_amd import protocols, workloads
+
+
+class OracleLattice:
+    """The Lattice interface over the CPU oracle."""
+
+    def __init__(self, model, L, seed, J=1.0, Delta=0.0):
+        self.model, self.L, self.seed, self.J, self.Delta = model, L, seed, J, Delta
+        self.s = oracle.init(model, L, seed)
+        self.t = 0
+        self.temps = []
+
+    def sweep(self, T, fuse_measure=False):
+        T = np.asarray(T, dtype=np.float64)
+        oracle.sweep(self.model, self.s, self.seed, self.J, self.Delta, self.t, T)
+        self.temps += list(T)
+        self.t += T.shape[0]
+
+    def measure(self, r=()):
+        r = np.asarray(r, dtype=np.uint32)
+        sums = oracle.measure(self.s, r)
+        d = oracle.derive(self.L, self.J, self.Delta, sums, r)
+        return dict(sums, t=self.t, e=d["e"], m=d["m"], xi=d["xi"], C_hat=d["C_hat"])
+
+
+def test_log_times():
+    ts = protocols.log_times(1000, 4)
+    assert ts[0] == 0 and ts[-1] == 1000
+    assert all(b > a for a, b in zip(ts, ts[1:]))
+    assert {1, 2, 4, 8, 16, 32, 64, 128, 256, 512} <= set(ts)
+    # about per_octave points per doubling once the grid is coarser than one sweep
+    assert 4 * 8 <= len([t for t in ts if 2 <= t <= 1000]) <= 4 * 9 + 1
+    assert protocols.log_times(0) == [0]
+    with pytest.raises(ValueError):
+        protocols.log_times(10, 0)
+
+
+def test_crossing_time_power_law():
+    """xi = A t^(1/z) is a straight line in (log t, log xi): the interpolated
+    crossing is the exact solution, rounded up to a whole sweep."""
+    A, z = 1.7, 2.17
+    times = protocols.log_times(20000, 8)
+    xi = [A * t ** (1.0 / z) for t in times]
+    for target in (3.3, 25.0, 99.5, 140.0):
+        exact = (target / A) ** z
+        assert protocols.crossing_time(times, xi, target) == math.ceil(exact - 1e-9)
+    assert protocols.crossing_time(times, xi, 1e6) is None
+
+
+def test_crossing_time_edges():
+    assert protocols.crossing_time([0, 4, 8], [5.0, 6.0, 7.0], 2.0) == 0  # already there at the start
+    # between t = 0 and the first point: linear in t
+    assert protocols.crossing_time([0, 10], [0.0, 10.0], 2.5) == 3
+    # the first crossing counts, not a later one after a dip
+    assert protocols.crossing_time([1, 2, 4, 8, 16], [1.0, 3.0, 2.0, 5.0, 6.0], 2.5) == 2
+    # a crossing never lands before the next whole sweep after the point below it
+    assert protocols.crossing_time([10, 11], [1.0, 100.0], 1.0000001) == 11
+    with pytest.raises(ValueError):
+        protocols.crossing_time([1, 1], [1.0, 2.0], 1.5)
+    with pytest.raises(ValueError):
+        protocols.crossing_time([1, 2], [1.0], 1.5)
+
+
+@pytest.mark.parametrize("model,T1,T2", [(0, 1.66, 2.3), (1, 1.24, 1.7)])
+def test_two_step_series_is_the_two_step_schedule(model, T1, T2):
+    """Protocol 2 through the driver equals one oracle run of the two-step
+    schedule (temperatures, final configuration, measured observables)."""
+    L, seed, t_switch = 64, workloads.seed_for(71), 21
+    r = workloads.r_sparse(L)
+    times = protocols.log_times(48, 2)
+    lat = OracleLattice(model, L, seed)
+    got = protocols.two_step_series(lat, T1, T2, t_switch, times, r)
+    T = oracle.schedule(1, [T1, t_switch, T2], 0, 48)
+    assert np.array_equal(np.array(lat.temps), T)
+    s = oracle.init(model, L, seed)
+    oracle.sweep(model, s, seed, 1.0, 0.0, 0, T)
+    assert np.array_equal(lat.s, s)
+    assert [m["t"] for m in got] == times
+    want = oracle.derive(L, 1.0, 0.0, oracle.measure(s, r), r)
+    assert got[-1]["e"] == want["e"] and got[-1]["xi"] == want["xi"]
+
+
+def test_switch_times_stop_at_the_largest_fraction():
+    """The T1 run stops at the first grid time where xi reaches max(f) xi_eq,
+    and every t_switch is the crossing of its own target on that series."""
+    L, seed = 128, workloads.seed_for(5)
+    r = workloads.r_sparse(L)
+    fs, xi_eq = (0.3, 0.5, 0.7), 12.0
+    lat = OracleLattice(0, L, seed)
+    t_sw, curve = protocols.switch_times(lat, 1.66, fs, xi_eq, r, t_limit=512, per_octave=4)
+    ts, xs = [m["t"] for m in curve], [m["xi"] for m in curve]
+    assert ts == [t for t in protocols.log_times(512, 4) if t <= ts[-1]]
+    assert xs[-1] >= max(fs) * xi_eq and all(x < max(fs) * xi_eq for x in xs[:-1])
+    assert lat.t == ts[-1] and set(lat.temps) == {1.66}
+    for f in fs:
+        assert t_sw[f] == protocols.crossing_time(ts, xs, f * xi_eq)
+    assert t_sw[0.3] <= t_sw[0.5] <= t_sw[0.7] <= ts[-1]
+    # an unreachable target within the limit gives None for that fraction
+    lat = OracleLattice(0, L, seed)
+    t_sw, curve = protocols.switch_times(lat, 1.66, (0.5, 50.0), xi_eq, r, t_limit=64, per_octave=2)
+    assert t_sw[50.0] is None and curve[-1]["t"] == 64 and t_sw[0.5] is not None
