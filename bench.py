@@ -212,6 +212,43 @@ def run_protocol2(args):
             "xi_at_t_max": [round(run[-1]["xi"], 2) for run in runs]}
 
 
+def run_ensemble(args):
+    """Ensemble of direct quenches at T_c (one batch), analysed as in the
+    paper's App. C (xi = I2/I1 with the r_cut / F-tail recipe) and App. D
+    (jackknife over replicas, fit of log t = z log xi + b)."""
+    import torch
+    from paper_2503_14688_amd import analysis, protocols, workloads
+    wl = workloads.ENSEMBLE_ISING
+    L, n = wl["L"], wl["replicas"]
+    r = workloads.r_sparse(L)
+    times = [t for t in protocols.log_times(wl["t_max"], wl["per_octave"]) if t >= 1]
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    data = protocols.quench_batch(wl["model"], L, [workloads.seed_for(wl["seed0"] + k) for k in range(n)],
+                                  wl["T"], times, r)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    xi, err, blocks = [], [], []
+    for d in data:
+        C = (d["Sx"] + d["Sy"]) / (2.0 * L * L)
+        x, e, _, blk = analysis.xi_ensemble(r, C, d["sum_s2"] / (float(L) * L))
+        xi.append(x)
+        err.append(e)
+        blocks.append(blk)
+    xi, err, blocks = np.array(xi), np.array(err), np.array(blocks).T
+    sel = np.array([t >= wl["fit_from"] for t in times])
+    fit = analysis.fit_z(np.array(times)[sel], xi[sel], err[sel], blocks[:, sel])
+    flips = float(L) * L * n * wl["t_max"]
+    log(f"ensemble: z = {fit['z']:.4f} +- {fit['z_err']:.4f}, {flips / wall / 1e9:.1f} flips/ns")
+    return {"workload": wl["name"], "replicas": n, "t_max": wl["t_max"], "wall_s": round(wall, 3),
+            "flips_per_ns": round(flips / wall / 1e9, 2),
+            "xi": {str(t): [round(float(a), 3), round(float(b), 3)] for t, a, b in zip(times, xi, err)
+                   if t in (16, 64, 256, 1024, 4096, 8192)},
+            "z_fit": {"z": round(fit["z"], 4), "z_err": round(fit["z_err"], 4),
+                      "chi2_dof": round(fit["chi2_dof"], 3), "t_window": [wl["fit_from"], wl["t_max"]]},
+            "z_paper": 2.1676}
+
+
 def run(args):
     import torch
     import paper_2503_14688_amd as spin
@@ -290,6 +327,8 @@ def run(args):
         out["serving"] = run_serving(args, sat)
     if not args.skip_protocol2:
         out["protocol2"] = run_protocol2(args)
+    if not args.skip_ensemble:
+        out["ensemble"] = run_ensemble(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
     return out
@@ -320,6 +359,7 @@ def main():
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--skip-protocol2", action="store_true")
+    ap.add_argument("--skip-ensemble", action="store_true")
     ap.add_argument("--replicas", type=int, default=512)
     ap.add_argument("--batch-sweeps", type=int, default=4096)
     ap.add_argument("--compare-sweeps", type=int, default=256)

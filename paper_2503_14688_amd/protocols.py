@@ -141,3 +141,30 @@ def two_step_batch(model, L, seeds, T1, T2, t_switches, times, r, J=1.0, Delta=0
     finally:
         b.close()
     return out
+
+
+def quench_batch(model, L, seeds, T, times, r, J=1.0, Delta=0.0):
+    """Protocol 1 for an ensemble of replicas (one per seed) as one batch.
+
+    Returns, per measurement time, a dict with t and the per-replica arrays
+    Sx, Sy (n_replicas, len(r)), sum_s2, e, m (n_replicas,): the input of the
+    ensemble analysis (jackknife over replicas)."""
+    t_max = int(max(times))
+    Tm = np.full((1, max(t_max, 1)), float(T))
+    reps = [dict(model=model, L=L, seed=int(s), J=J, Delta=Delta, schedule=0) for s in seeds]
+    b = Batch(reps, Tm).init_random()
+    out = []
+    t_now = 0
+    try:
+        for t in times:
+            if int(t) > t_now:
+                b.run(int(t) - t_now)
+                t_now = int(t)
+            ms = b.measure_all(r)
+            out.append({"t": t_now,
+                        "Sx": np.stack([m["Sx"] for m in ms]), "Sy": np.stack([m["Sy"] for m in ms]),
+                        "sum_s2": np.array([m["sum_s2"] for m in ms], dtype=np.float64),
+                        "e": np.array([m["e"] for m in ms]), "m": np.array([m["m"] for m in ms])})
+    finally:
+        b.close()
+    return out

@@ -72,6 +72,13 @@ PROTOCOL2_ISING = dict(name="protocol2_ising_L65536", model=0, L=1 << 16, T1=1.6
                        t_limit=16384, seed=SEED_BASE)
 
 
+# Ensemble of direct quenches for the analysis of App. C and D: 64 Ising
+# replicas of L = 4096 at T_c measured on a grid of two times per octave up to
+# t = 8192 (xi grows to about 40, L / xi > 100), z fitted from t = 256 on.
+ENSEMBLE_ISING = dict(name="ensemble_ising_L4096_tc", model=0, L=1 << 12, replicas=64, T=TC_ISING,
+                      t_max=8192, per_octave=2, fit_from=256, seed0=1000)
+
+
 def batched_replicas(n=512, sizes=(256, 512, 1024, 2048), taus=(64.0, 256.0, 1024.0)):
     """Replica descriptors of the batched exponential-schedule workload:
     uniform mix of sizes, half Ising and half Blume-Capel (Delta = 0), tau

@@ -73,3 +73,26 @@ def test_two_step_batch_matches_solo_runs(gpu):
     assert any(a["e"] != b["e"] for a, b in zip(runs[0], runs[1]) if a["t"] > 13)
     with pytest.raises(ValueError):
         protocols.two_step_batch(model, L, seeds[:2], T1, T2, t_switches, times, r)
+
+
+def test_quench_batch_matches_solo_runs(gpu):
+    """The ensemble driver's per-replica sums equal solo runs of each seed,
+    and the ensemble analysis runs on them."""
+    from paper_2503_14688_amd import analysis
+    L, T = 128, workloads.TC_ISING
+    seeds = [workloads.seed_for(60 + k) for k in range(4)]
+    r = workloads.r_sparse(L)
+    times = [1, 2, 4, 8, 16, 32]
+    data = protocols.quench_batch(0, L, seeds, T, times, r)
+    assert [d["t"] for d in data] == times
+    for k, s in enumerate(seeds):
+        lat = gpu.Lattice(0, L, s).init_random()
+        for d in data:
+            lat.sweep(np.full(d["t"] - lat.t, T))
+            m = lat.measure(r)
+            assert np.array_equal(d["Sx"][k], m["Sx"]) and np.array_equal(d["Sy"][k], m["Sy"])
+            assert d["sum_s2"][k] == m["sum_s2"] and d["e"][k] == m["e"]
+        lat.close()
+    C = (data[-1]["Sx"] + data[-1]["Sy"]) / (2.0 * L * L)
+    xi, err, full, blocks = analysis.xi_ensemble(r, C, data[-1]["sum_s2"] / (L * L))
+    assert xi > 0 and err >= 0 and blocks.shape == (4,)
