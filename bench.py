@@ -194,6 +194,8 @@ def run_protocol2(args):
     sweeps_a = lat.t
     lat.close()
     del lat
+    torch.cuda.synchronize()
+    wall_a = time.perf_counter() - wall0
     if any(t_sw[f] is None for f in fs):
         raise RuntimeError(f"xi did not reach f xi_eq within {wl['t_limit']} sweeps at T1: {t_sw}")
     tsw = [t_sw[f] for f in fs]
@@ -207,6 +209,7 @@ def run_protocol2(args):
             "t_switch": tsw, "t_switch_paper": list(wl["t_switch_paper"]),
             "xi_at_T1": {str(m["t"]): round(m["xi"], 3) for m in curve if m["t"] in (256, 1024, 4096)},
             "t_max": wl["t_max"], "sweeps_at_T1": sweeps_a, "wall_s": round(wall, 3),
+            "wall_T1_run_s": round(wall_a, 3), "measurements_at_T1": len(curve),
             "flips_per_ns": round(flips / wall / 1e9, 2),
             "E_at_t_max": [round(run[-1]["e"], 6) for run in runs],
             "xi_at_t_max": [round(run[-1]["xi"], 2) for run in runs]}

@@ -27,6 +27,7 @@ struct spin_batch {
     bool own_stream = false;
     uint64_t t = 0;                      // sweeps done (schedule step)
     int variant = -1;                    // sweep strategy in use (-1: tune at first run)
+    int models = 0;                      // spin::BatchModels bits of the replicas
     spin::BatchReplica *d_reps[2] = {nullptr, nullptr};  // per tile shape
     uint32_t *d_tile_rep[2] = {nullptr, nullptr};
     uint64_t ntiles[2] = {0, 0};
@@ -107,8 +108,8 @@ int launch_sweeps(spin_batch *b, int variant, uint64_t t0, uint32_t n, hipStream
     for (uint32_t q = 0; q < n; ++q) {
         const uint64_t step = t0 + q;
         for (uint32_t c = 0; c < 2; ++c)
-            HIP_TRY(spin::launch_batch_half_sweep(variant, b->d_reps[k], b->d_tile_rep[k], b->ntiles[k],
-                                                  b->d_tables, b->n_steps, (uint32_t)step, c, st),
+            HIP_TRY(spin::launch_batch_half_sweep(variant, b->models, b->d_reps[k], b->d_tile_rep[k],
+                                                  b->ntiles[k], b->d_tables, b->n_steps, (uint32_t)step, c, st),
                     "batched sweep launch");
     }
     return 0;
@@ -260,6 +261,7 @@ int spin_batch_create(uint32_t n, const spin_replica_desc *descs, uint32_t n_sch
             return fail(rc, "replica %u: %s", r, msg.c_str());
         }
         h->t = d.t0;
+        b->models |= d.model == SPIN_ISING ? spin::kBatchIsing : spin::kBatchBc;
         b->reps.push_back(h);
         b->t0.push_back(d.t0);
         auto key = std::make_tuple(d.model, d.J, d.Delta, d.schedule);

@@ -19,21 +19,6 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Blocks of a persistent kernel that are resident at once on the current
-// device (occupancy x compute units), so a grid-stride loop has no tail wave.
-template <typename K>
-unsigned resident_grid(K kernel, size_t dyn_lds, uint64_t tiles)
-{
-    int dev = 0, cus = 0, per_cu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kernel, kBlock, dyn_lds);
-    uint64_t g = (uint64_t)(cus > 0 ? cus : 256) * (uint64_t)(per_cu > 0 ? per_cu : 1);
-    if (g > tiles)
-        g = tiles;
-    return (unsigned)(g ? g : 1);
-}
-
 inline unsigned grid_for(uint64_t items)
 {
     uint64_t b = (items + kBlock - 1) / kBlock;
@@ -732,6 +717,18 @@ union AnyList {
     BcList<kBcGroups, bc_list_cap(V), variant_rows(V)> gen;
 };
 
+template <int V>
+struct IsingList {
+    WaveList<variant_list_cap(V)> ising;
+};
+
+// LDS of the batched kernel, per wavefront: only the lists of the models the
+// batch holds (an Ising-only batch keeps the Ising kernel's smaller LDS, so
+// as many blocks fit on a CU as in the single-lattice launch).
+template <int V, int MODELS>
+using BatchList = std::conditional_t<MODELS == kBatchIsing, IsingList<V>,
+                                     std::conditional_t<MODELS == kBatchBc, BcListUnion<V>, AnyList<V>>>;
+
 template <bool MEASURE, int V>
 __global__ __launch_bounds__(kBlock) void k_sweep_ising(Lattice lat, uint32_t c, uint32_t t, GroupTable gt,
                                                         unsigned long long *acc)
@@ -790,39 +787,64 @@ __global__ __launch_bounds__(kBlock) void k_sweep_bc(Lattice lat, uint32_t c, ui
 // flat tile list maps each global tile to (replica, local tile); replica r's
 // thresholds for this sweep are tables[sched(r) * stride + step] and its
 // random stream runs at sweep index t0(r) + step.
-template <int V>
-__global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica *reps, const uint32_t *tile_rep,
-                                                             uint64_t ntiles, const GroupTable *tables,
-                                                             uint32_t stride, uint32_t step, uint32_t c)
+// A copy of *p in scalar registers (p is the same for the whole wavefront).
+template <typename T>
+__device__ __forceinline__ T wave_uniform_copy(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
+    T out;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(p);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&out);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k)
+        dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+    return out;
+}
+
+template <int V, int MODELS>
+__global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica *__restrict__ reps,
+                                                             const uint32_t *__restrict__ tile_rep, uint64_t ntiles,
+                                                             const GroupTable *__restrict__ tables, uint32_t stride,
+                                                             uint32_t step, uint32_t c)
 {
     constexpr int R = variant_rows(V);
-    __shared__ std::conditional_t<variant_compact(V), AnyList<V>, int> Q[kWaves];
+    __shared__ std::conditional_t<variant_compact(V), BatchList<V, MODELS>, int> Q[kWaves];
     unsigned long long e[kEmCounters] = {0, 0, 0, 0};
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t rid = tile_rep[tile];
-        const BatchReplica &rep = reps[rid];
-        const GroupTable &gt = tables[(size_t)rep.sched * stride + step];
+        // The tile, hence its replica, is the same for the whole block: keep
+        // the descriptor and thresholds in scalar registers, as the
+        // single-lattice kernel has them (its arguments), so that addresses,
+        // keys and the row-uniform Philox rounds stay scalar.
+        const uint32_t rid = __builtin_amdgcn_readfirstlane(tile_rep[tile]);
+        const BatchReplica rep = wave_uniform_copy(reps + rid);
+        const GroupTable gt = wave_uniform_copy(tables + (size_t)rep.sched * stride + step);
         const uint64_t local = tile - rep.tile0;
         const uint32_t t = rep.t0 + step;
-        if constexpr (variant_compact(V)) {
-            if (rep.lat.model == kIsing) {
-                if (rep.lat.W % kBlock == 0)
-                    ising_tile_compact<false, R, true>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].ising, e);
+        if (rep.lat.model == kIsing) {
+            if constexpr ((MODELS & kBatchIsing) != 0) {
+                if constexpr (variant_compact(V)) {
+                    if (rep.lat.W % kBlock == 0)
+                        ising_tile_compact<false, R, true>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].ising, e);
+                    else
+                        ising_tile_compact<false, R, false>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].ising, e);
+                } else if (rep.lat.W % kBlock == 0) {
+                    ising_tile_lazy<false, R, true>(rep.lat, c, t, gt, local, e);
+                } else {
+                    ising_tile_lazy<false, R, false>(rep.lat, c, t, gt, local, e);
+                }
+            }
+        } else if constexpr ((MODELS & kBatchBc) != 0) {
+            if constexpr (variant_compact(V)) {
+                if (rep.lat.bc_groups == kBcGroupsDelta0)
+                    bc_tile_compact<false, R, kBcGroupsDelta0>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].d0, e);
                 else
-                    ising_tile_compact<false, R, false>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].ising, e);
-            } else if (rep.lat.bc_groups == kBcGroupsDelta0)
-                bc_tile_compact<false, R, kBcGroupsDelta0>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].d0, e);
-            else
-                bc_tile_compact<false, R, kBcGroups>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].gen, e);
-        } else if (rep.lat.model == kIsing) {
-            if (rep.lat.W % kBlock == 0)
-                ising_tile_lazy<false, R, true>(rep.lat, c, t, gt, local, e);
-            else
-                ising_tile_lazy<false, R, false>(rep.lat, c, t, gt, local, e);
-        } else if (rep.lat.bc_groups == kBcGroupsDelta0)
-            bc_tile<false, R, kBcGroupsDelta0>(rep.lat, c, t, gt, local, e);
-        else
-            bc_tile<false, R, kBcGroups>(rep.lat, c, t, gt, local, e);
+                    bc_tile_compact<false, R, kBcGroups>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].gen, e);
+            } else if (rep.lat.bc_groups == kBcGroupsDelta0) {
+                bc_tile<false, R, kBcGroupsDelta0>(rep.lat, c, t, gt, local, e);
+            } else {
+                bc_tile<false, R, kBcGroups>(rep.lat, c, t, gt, local, e);
+            }
+        }
     }
 }
 
@@ -1050,26 +1072,43 @@ uint64_t sweep_tiles(const Lattice &lat, int rows)
     return rows == 4 ? tiles_of<4>(lat) : tiles_of<8>(lat);
 }
 
-template <int V>
-hipError_t launch_batch_v(const BatchReplica *reps, const uint32_t *tile_rep, uint64_t ntiles,
-                          const GroupTable *tables, uint32_t stride, uint32_t step, uint32_t colour, hipStream_t st)
+template <int V, int MODELS>
+hipError_t launch_batch_vm(const BatchReplica *reps, const uint32_t *tile_rep, uint64_t ntiles,
+                           const GroupTable *tables, uint32_t stride, uint32_t step, uint32_t colour, hipStream_t st)
 {
-    static const unsigned g = resident_grid(k_batch_half_sweep<V>, 0, ~0ull);
-    hipLaunchKernelGGL(k_batch_half_sweep<V>, dim3(g < ntiles ? g : (unsigned)ntiles), dim3(kBlock), 0, st, reps,
-                       tile_rep, ntiles, tables, stride, step, colour);
+    // The single-lattice launch's grid: up to 65536 blocks, a block walks
+    // tiles by grid stride.  (A grid of only the resident blocks, each walking
+    // dozens of tiles, measured about 25% slower on large replicas: the
+    // hardware's block dispatch overlaps one tile's start with another's end
+    // better than a persistent block does.)
+    constexpr unsigned g = 65536u;
+    hipLaunchKernelGGL((k_batch_half_sweep<V, MODELS>), dim3(g < ntiles ? g : (unsigned)ntiles), dim3(kBlock), 0,
+                       st, reps, tile_rep, ntiles, tables, stride, step, colour);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_half_sweep(int variant, const BatchReplica *reps, const uint32_t *tile_rep,
+template <int V>
+hipError_t launch_batch_v(int models, const BatchReplica *reps, const uint32_t *tile_rep, uint64_t ntiles,
+                          const GroupTable *tables, uint32_t stride, uint32_t step, uint32_t colour, hipStream_t st)
+{
+    switch (models) {
+    case kBatchIsing: return launch_batch_vm<V, kBatchIsing>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
+    case kBatchBc: return launch_batch_vm<V, kBatchBc>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
+    case kBatchMixed: return launch_batch_vm<V, kBatchMixed>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_half_sweep(int variant, int models, const BatchReplica *reps, const uint32_t *tile_rep,
                                    uint64_t ntiles, const GroupTable *tables, uint32_t stride, uint32_t step,
                                    uint32_t colour, hipStream_t st)
 {
     switch (variant) {
-    case 0: return launch_batch_v<0>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
-    case 1: return launch_batch_v<1>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
-    case 2: return launch_batch_v<2>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
-    case 3: return launch_batch_v<3>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
-    case 4: return launch_batch_v<4>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
+    case 0: return launch_batch_v<0>(models, reps, tile_rep, ntiles, tables, stride, step, colour, st);
+    case 1: return launch_batch_v<1>(models, reps, tile_rep, ntiles, tables, stride, step, colour, st);
+    case 2: return launch_batch_v<2>(models, reps, tile_rep, ntiles, tables, stride, step, colour, st);
+    case 3: return launch_batch_v<3>(models, reps, tile_rep, ntiles, tables, stride, step, colour, st);
+    case 4: return launch_batch_v<4>(models, reps, tile_rep, ntiles, tables, stride, step, colour, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -70,7 +70,10 @@ hipError_t launch_init(const Lattice &lat, hipStream_t st);
 // rows-per-thread choice (4 or 8), and the batched half-sweep over a flat
 // tile list of many lattices.
 uint64_t sweep_tiles(const Lattice &lat, int rows);
-hipError_t launch_batch_half_sweep(int variant, const BatchReplica *reps, const uint32_t *tile_rep,
+// Models present in a batch (bit 0 Ising, bit 1 Blume-Capel): the batched
+// kernel is specialised on it.
+enum BatchModels : int { kBatchIsing = 1, kBatchBc = 2, kBatchMixed = 3 };
+hipError_t launch_batch_half_sweep(int variant, int models, const BatchReplica *reps, const uint32_t *tile_rep,
                                    uint64_t ntiles, const GroupTable *tables, uint32_t stride, uint32_t step,
                                    uint32_t colour, hipStream_t st);
 hipError_t launch_half_sweep(const Lattice &lat, uint32_t colour, uint32_t t, const GroupTable &gt,

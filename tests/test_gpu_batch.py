@@ -150,3 +150,21 @@ def test_batch_measure_all(gpu):
     with pytest.raises(gpu.SpinError):
         b.measure_all([64])  # not below L = 64 of the smallest replica
     b.close()
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_single_model_batches(gpu, model):
+    """A batch of one model runs the batched kernel specialised on that model
+    (the Ising one keeps the single-lattice kernel's smaller LDS): every
+    strategy reproduces the oracle."""
+    reps = [rep for rep in mixed_replicas() if rep["model"] == model]
+    n = 12
+    T = schedules(n)
+    want = [oracle_run(rep, T[rep["schedule"]], n) for rep in reps]
+    for v in range(5):
+        b = gpu.Batch(reps, T).init_random()
+        b.run(n, gpu.BATCH_VARIANT(v))
+        b.sync()
+        for k in range(len(reps)):
+            assert np.array_equal(b.spins(k), want[k]), (v, k)
+        b.close()
