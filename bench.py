@@ -42,6 +42,12 @@ MEASURED_TRAFFIC = {
     ("bc_L262144_t16937", 2): 26.95e9,
 }
 MEASURED_WITH = "5e5519478718c7c6"
+# (workload, sweep strategy): wave instructions per 64 words of a colour plane
+# (SQ_INSTS_VALU, SQ_INSTS_SALU) from the same counter pass
+MEASURED_ISSUE = {
+    ("ising_L1048576_tc", 2): (151.1, 150.6),
+    ("bc_L262144_t16937", 2): (456.0, 82.6),
+}
 
 
 def sweep_sources_hash():
@@ -56,6 +62,22 @@ def measured_traffic(workload, strategy):
     if sweep_sources_hash() != MEASURED_WITH:
         return None
     return MEASURED_TRAFFIC.get((workload, strategy))
+
+
+def issue_busy(workload, strategy, words_per_launch, launch_s, clock_hz=2.34e9):
+    """Busy fractions of the vector and scalar issue of the sweep kernel:
+    measured wave instructions per 64 words x words per launch over the
+    launch's cycles (1024 SIMDs at one vector instruction per 4 cycles; 256
+    scalar units at one instruction per cycle; clock as measured with the
+    counters).  None unless the counters were taken on these sources."""
+    if sweep_sources_hash() != MEASURED_WITH or (workload, strategy) not in MEASURED_ISSUE:
+        return None
+    valu, salu = MEASURED_ISSUE[(workload, strategy)]
+    cycles = launch_s * clock_hz
+    waves = words_per_launch / 64.0
+    return {"valu": round(valu * waves * 4 / (1024 * cycles), 3), "salu": round(salu * waves / (256 * cycles), 3),
+            "clock_ghz": clock_hz / 1e9, "source": "profiles/issue_rates_ising_L1048576_bc_L262144.txt",
+            "note": "valu counts 4 cycles per vector instruction; two-operand forms issue in 2, so above 1 is possible"}
 
 
 def log(msg):
@@ -316,6 +338,7 @@ def run(args):
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "binding_unit": "valu",
+                     "issue_busy": issue_busy(wl["name"], strategy, float(L) * L / 64, half_sweep_s),
                      "kernel": "k_sweep_ising" if model == 0 else "k_sweep_bc",
                      "avg_launch_ms": round(half_sweep_s * 1e3, 3),
                      "algorithmic_bytes_per_launch": bytes_launch},
