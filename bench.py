@@ -399,7 +399,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab decomposition "
-              "is a design, not part of this build", file=sys.stderr)
+              "is not implemented", file=sys.stderr)
         sys.exit(2)
     print(json.dumps(run(args)), flush=True)
 
