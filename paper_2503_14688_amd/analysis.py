@@ -206,3 +206,35 @@ def fit_z(t, xi, xi_err, xi_blocks=None):
         zs = np.array([one(np.asarray(blk, dtype=np.float64), z)[0] for blk in xi_blocks])
         out["z_err"] = float(jackknife_error(zs))
     return out
+
+
+def fit_z_energy(t, dE, dE_err, dE_blocks=None, z0=2.17):
+    """z from the excess energy of the Ising quench to T_c (App. D):
+    E(t) - E_eq = b t^(-1/z) + b' t^(-2/z), E_eq = -sqrt(2) known exactly,
+    fitted by weighted least squares for (b, b', z); with dE_blocks
+    (n_replicas, len(t)) of leave-one-out excess energies the fit is repeated
+    per block for the jackknife error of z.  (The paper adds a third term,
+    b'' t^(-(omega + 1)/z), for its longer times.)
+    Returns dict(z, b, b2, z_err, chi2_dof)."""
+    from scipy.optimize import curve_fit
+    t = np.asarray(t, dtype=np.float64)
+    dE = np.asarray(dE, dtype=np.float64)
+    dE_err = np.asarray(dE_err, dtype=np.float64)
+    if t.shape[0] < 4:
+        raise ValueError("need at least four times")
+
+    def model(x, b, b2, inv_z):
+        return b * x ** (-inv_z) + b2 * x ** (-2.0 * inv_z)
+
+    def one(y, p0):
+        p, _ = curve_fit(model, t, y, p0=p0, sigma=dE_err, maxfev=20000)
+        return p
+
+    p0 = (float(dE[0] * t[0] ** (1.0 / z0)), 0.0, 1.0 / z0)
+    p = one(dE, p0)
+    chi2 = float((((dE - model(t, *p)) / dE_err) ** 2).sum())
+    out = dict(z=float(1.0 / p[2]), b=float(p[0]), b2=float(p[1]), chi2_dof=chi2 / (t.shape[0] - 3), z_err=None)
+    if dE_blocks is not None:
+        zs = np.array([1.0 / one(np.asarray(blk, dtype=np.float64), p)[2] for blk in dE_blocks])
+        out["z_err"] = float(jackknife_error(zs))
+    return out

@@ -98,3 +98,19 @@ def test_c_hat_definition():
     m = {"Sx": np.array([10, -4]), "Sy": np.array([6, 0]), "sum_s2": 12}
     C, C0 = analysis.c_hat(m, 4)
     assert np.array_equal(C, np.array([0.5, -0.125])) and C0 == 0.75
+
+
+def test_fit_z_energy_two_terms():
+    """E - E_eq = b t^(-1/z) + b' t^(-2/z): the fit returns z exactly on
+    exact data and a jackknife error that covers it on noisy replicas."""
+    z, b, b2 = 2.1676, 0.31, -0.12
+    t = np.array([16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192], dtype=np.float64)
+    dE = b * t ** (-1 / z) + b2 * t ** (-2 / z)
+    res = analysis.fit_z_energy(t, dE, 1e-3 * dE)
+    assert res["z"] == pytest.approx(z, rel=1e-8) and res["b"] == pytest.approx(b, rel=1e-6)
+    rng = np.random.default_rng(4)
+    reps = dE[None, :] + 0.002 * dE[None, :] * rng.normal(size=(48, t.shape[0]))
+    mean = reps.mean(axis=0)
+    err = reps.std(axis=0, ddof=1) / math.sqrt(48)
+    res = analysis.fit_z_energy(t, mean, err, analysis.jackknife_means(reps))
+    assert abs(res["z"] - z) < 5 * res["z_err"] and res["z_err"] < 0.1
