@@ -112,3 +112,20 @@ def test_switch_times_stop_at_the_largest_fraction():
     lat = OracleLattice(0, L, seed)
     t_sw, curve = protocols.switch_times(lat, 1.66, (0.5, 50.0), xi_eq, r, t_limit=64, per_octave=2)
     assert t_sw[50.0] is None and curve[-1]["t"] == 64 and t_sw[0.5] is not None
+
+
+@pytest.mark.parametrize("t_switch", [0, 48, 1000])
+def test_two_step_degenerate_switch_times(t_switch):
+    """t_switch = 0 is a quench to T2, t_switch >= t_max a quench to T1."""
+    L, seed, T1, T2 = 64, workloads.seed_for(9), 1.66, 2.4
+    r = workloads.r_sparse(L)
+    lat = OracleLattice(0, L, seed)
+    protocols.two_step_series(lat, T1, T2, t_switch, [0, 8, 48], r)
+    assert lat.temps == [T2] * 48 if t_switch == 0 else lat.temps == [T1] * 48
+
+
+def test_series_rejects_times_in_the_past():
+    lat = OracleLattice(0, 64, 1)
+    protocols.series(lat, np.full(16, 2.0), [8], workloads.r_sparse(64))
+    with pytest.raises(ValueError):
+        protocols.series(lat, np.full(16, 2.0), [4], workloads.r_sparse(64))
