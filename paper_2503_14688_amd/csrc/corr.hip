@@ -502,7 +502,7 @@ __device__ __forceinline__ void y_walk(const Lattice &lat, int n_r, uint32_t RIN
     const uint32_t total = lines ? strips / 8u : strips;
     const uint32_t xcd = blockIdx.x % 8u, m = blockIdx.x / 8u;
     const uint32_t first = lines ? xcd * (gridDim.x / 64u) + m / 8u : blockIdx.x;
-    // global loads run one chunk ahead of the chunk being paired
+    // each group loads its chunks four chunks ahead of the chunk being paired
     for (uint32_t unit = first; unit < total; unit += per_iter) {
         const uint32_t strip = lines ? unit * 8u + m % 8u : unit;
         const uint32_t w0 = strip * SW;
