@@ -38,15 +38,16 @@ SWEEP_SOURCES = ["paper_2503_14688_amd/csrc/kernels.hip", "paper_2503_14688_amd/
                  "paper_2503_14688_amd/csrc/kernels.hpp"]
 MEASURED_TRAFFIC = {
     # (workload, sweep strategy): bytes per launch
-    ("ising_L1048576_tc", 2): 220.91e9,
-    ("bc_L262144_t16937", 2): 26.95e9,
+    ("ising_L1048576_tc", 2): 221.93e9,
+    ("bc_L262144_t16937", 2): 26.90e9,
 }
-MEASURED_WITH = "5e5519478718c7c6"
+MEASURED_WITH = "1a2b399b3d07df86"
 # (workload, sweep strategy): wave instructions per 64 words of a colour plane
-# (SQ_INSTS_VALU, SQ_INSTS_SALU) from the same counter pass
+# (SQ_INSTS_VALU, SQ_INSTS_SALU) and the clock (GHz, GRBM_GUI_ACTIVE over the
+# dispatch) from the same counter pass
 MEASURED_ISSUE = {
-    ("ising_L1048576_tc", 2): (151.1, 150.6),
-    ("bc_L262144_t16937", 2): (456.0, 82.6),
+    ("ising_L1048576_tc", 2): (162.2, 95.9, 2.18),
+    ("bc_L262144_t16937", 2): (456.0, 82.6, 2.39),
 }
 
 
@@ -64,7 +65,7 @@ def measured_traffic(workload, strategy):
     return MEASURED_TRAFFIC.get((workload, strategy))
 
 
-def issue_busy(workload, strategy, words_per_launch, launch_s, clock_hz=2.34e9):
+def issue_busy(workload, strategy, words_per_launch, launch_s):
     """Busy fractions of the vector and scalar issue of the sweep kernel:
     measured wave instructions per 64 words x words per launch over the
     launch's cycles (1024 SIMDs at one vector instruction per 4 cycles; 256
@@ -72,11 +73,11 @@ def issue_busy(workload, strategy, words_per_launch, launch_s, clock_hz=2.34e9):
     counters).  None unless the counters were taken on these sources."""
     if sweep_sources_hash() != MEASURED_WITH or (workload, strategy) not in MEASURED_ISSUE:
         return None
-    valu, salu = MEASURED_ISSUE[(workload, strategy)]
-    cycles = launch_s * clock_hz
+    valu, salu, ghz = MEASURED_ISSUE[(workload, strategy)]
+    cycles = launch_s * ghz * 1e9
     waves = words_per_launch / 64.0
     return {"valu": round(valu * waves * 4 / (1024 * cycles), 3), "salu": round(salu * waves / (256 * cycles), 3),
-            "clock_ghz": clock_hz / 1e9, "source": "profiles/issue_rates_ising_L1048576_bc_L262144.txt",
+            "clock_ghz": ghz, "source": "profiles/issue_rates_ising_L1048576_bc_L262144.txt",
             "note": "valu counts 4 cycles per vector instruction; two-operand forms issue in 2, so above 1 is possible"}
 
 
