@@ -361,10 +361,17 @@ def run(args):
     if not args.skip_serving:
         sat = out["batched"]["flips_per_ns"] if "batched" in out else out["sweep_only_flips_per_ns"]
         out["serving"] = run_serving(args, sat)
-    if not args.skip_protocol2:
-        out["protocol2"] = run_protocol2(args)
-    if not args.skip_ensemble:
-        out["ensemble"] = run_ensemble(args)
+    # the extra sections report an error instead of losing the line
+    for name, skip, fn in (("protocol2", args.skip_protocol2, run_protocol2),
+                           ("ensemble", args.skip_ensemble, run_ensemble)):
+        if skip:
+            continue
+        try:
+            out[name] = fn(args)
+        except Exception as exc:  # noqa: BLE001
+            log(f"{name} failed: {exc!r}")
+            out[name] = {"error": repr(exc)}
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
     return out
