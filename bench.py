@@ -238,13 +238,11 @@ def run_protocol2(args):
             "xi_at_t_max": [round(run[-1]["xi"], 2) for run in runs]}
 
 
-def run_ensemble(args):
-    """Ensemble of direct quenches at T_c (one batch), analysed as in the
-    paper's App. C (xi = I2/I1 with the r_cut / F-tail recipe) and App. D
-    (jackknife over replicas, fit of log t = z log xi + b)."""
+def _ensemble_z(wl):
+    """One model's ensemble of direct quenches (one batch) with xi(t) by the
+    App. C recipe and z from log t = z log xi + b (App. D), jackknife errors."""
     import torch
     from paper_2503_14688_amd import analysis, protocols, workloads
-    wl = workloads.ENSEMBLE_ISING
     L, n = wl["L"], wl["replicas"]
     r = workloads.r_sparse(L)
     times = [t for t in protocols.log_times(wl["t_max"], wl["per_octave"]) if t >= 1]
@@ -264,24 +262,35 @@ def run_ensemble(args):
     xi, err, blocks = np.array(xi), np.array(err), np.array(blocks).T
     sel = np.array([t >= wl["fit_from"] for t in times])
     fit = analysis.fit_z(np.array(times)[sel], xi[sel], err[sel], blocks[:, sel])
-    # excess energy over E_eq(T_c) = -sqrt(2) (Ising), same window
-    dE = np.array([d["e"] for d in data]).T + math.sqrt(2.0)  # (replicas, times)
-    sel_e = sel
-    fit_e = analysis.fit_z_energy(np.array(times)[sel_e], dE.mean(axis=0)[sel_e],
-                                  dE.std(axis=0, ddof=1)[sel_e] / math.sqrt(n),
-                                  analysis.jackknife_means(dE)[:, sel_e])
     flips = float(L) * L * n * wl["t_max"]
-    log(f"ensemble: z = {fit['z']:.4f} +- {fit['z_err']:.4f} (xi), {fit_e['z']:.4f} +- {fit_e['z_err']:.4f} "
-        f"(energy), {flips / wall / 1e9:.1f} flips/ns")
-    return {"workload": wl["name"], "replicas": n, "t_max": wl["t_max"], "wall_s": round(wall, 3),
-            "flips_per_ns": round(flips / wall / 1e9, 2),
-            "xi": {str(t): [round(float(a), 3), round(float(b), 3)] for t, a, b in zip(times, xi, err)
-                   if t in (16, 64, 256, 1024, 4096, 8192)},
-            "z_fit": {"z": round(fit["z"], 4), "z_err": round(fit["z_err"], 4),
-                      "chi2_dof": round(fit["chi2_dof"], 3), "t_window": [wl["fit_from"], wl["t_max"]]},
-            "z_fit_energy": {"z": round(fit_e["z"], 4), "z_err": round(fit_e["z_err"], 4),
-                             "chi2_dof": round(fit_e["chi2_dof"], 3), "t_window": [wl["fit_from"], wl["t_max"]]},
-            "z_paper": 2.1676}
+    out = {"workload": wl["name"], "replicas": n, "t_max": wl["t_max"], "wall_s": round(wall, 3),
+           "flips_per_ns": round(flips / wall / 1e9, 2),
+           "xi": {str(t): [round(float(a), 3), round(float(b), 3)] for t, a, b in zip(times, xi, err)
+                  if t in (16, 64, 256, 1024, 4096, 8192)},
+           "z_fit": {"z": round(fit["z"], 4), "z_err": round(fit["z_err"], 4),
+                     "chi2_dof": round(fit["chi2_dof"], 3), "t_window": [wl["fit_from"], wl["t_max"]]}}
+    if wl["model"] == 0:
+        # excess energy over E_eq(T_c) = -sqrt(2), known exactly for Ising only
+        dE = np.array([d["e"] for d in data]).T + math.sqrt(2.0)  # (replicas, times)
+        fit_e = analysis.fit_z_energy(np.array(times)[sel], dE.mean(axis=0)[sel],
+                                      dE.std(axis=0, ddof=1)[sel] / math.sqrt(n),
+                                      analysis.jackknife_means(dE)[:, sel])
+        out["z_fit_energy"] = {"z": round(fit_e["z"], 4), "z_err": round(fit_e["z_err"], 4),
+                               "chi2_dof": round(fit_e["chi2_dof"], 3), "t_window": [wl["fit_from"], wl["t_max"]]}
+    log(f"ensemble {wl['name']}: z = {fit['z']:.4f} +- {fit['z_err']:.4f} (xi)"
+        + (f", {out['z_fit_energy']['z']:.4f} +- {out['z_fit_energy']['z_err']:.4f} (energy)"
+           if "z_fit_energy" in out else "") + f", {flips / wall / 1e9:.1f} flips/ns")
+    return out
+
+
+def run_ensemble(args):
+    """Ising and Blume-Capel ensembles at their critical temperatures: the
+    paper's universality check, one z per model (its value: 2.1676(1))."""
+    from paper_2503_14688_amd import workloads
+    out = _ensemble_z(workloads.ENSEMBLE_ISING)
+    out["z_paper"] = 2.1676
+    out["blume_capel"] = _ensemble_z(workloads.ENSEMBLE_BC)
+    return out
 
 
 def run(args):

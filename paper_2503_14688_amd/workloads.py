@@ -77,6 +77,10 @@ PROTOCOL2_ISING = dict(name="protocol2_ising_L65536", model=0, L=1 << 16, T1=1.6
 # t = 8192 (xi grows to about 40, L / xi > 100), z fitted from t = 256 on.
 ENSEMBLE_ISING = dict(name="ensemble_ising_L4096_tc", model=0, L=1 << 12, replicas=64, T=TC_ISING,
                       t_max=8192, per_octave=2, fit_from=256, seed0=1000)
+# The same for Blume-Capel (Delta = 0) at its T_c (Table I): the paper's
+# universality claim is one z for both models.
+ENSEMBLE_BC = dict(name="ensemble_bc_L4096_tc", model=1, L=1 << 12, replicas=64, T=TC_BC,
+                   t_max=8192, per_octave=2, fit_from=256, seed0=2000)
 
 
 def batched_replicas(n=512, sizes=(256, 512, 1024, 2048), taus=(64.0, 256.0, 1024.0)):
