@@ -177,6 +177,12 @@ __device__ __forceinline__ uint32_t stream_tag(uint32_t purpose, uint32_t colour
 //
 // apply_block consumes the four planes of block blk; metropolis_accept runs
 // the whole lazy test for one word.
+//
+// The plane's threshold bit of each group is the same for every lane.  With
+// two groups it enters as a scalar mask (one vector AND-OR per group); with
+// the Blume-Capel group counts (6 or 13) each group whose bit is set adds
+// its sites under a wave-uniform branch, so the vector unit does one OR per
+// set bit and the scalar unit, otherwise idle there, does the tests.
 template <int NG>
 __device__ __forceinline__ void apply_block(const Block4 &r, uint32_t blk, const uint32_t (&need)[NG],
                                             const uint32_t (&thr)[NG], uint32_t &undecided, uint32_t &accepted)
@@ -185,9 +191,19 @@ __device__ __forceinline__ void apply_block(const Block4 &r, uint32_t blk, const
     for (int q = 0; q < 4; ++q) {
         const uint32_t shift = 31u - (4u * blk + (uint32_t)q);
         uint32_t tb = 0;
+        if constexpr (NG > 2) {
 #pragma unroll
-        for (int g = 0; g < NG; ++g)
-            tb |= need[g] & (0u - ((thr[g] >> shift) & 1u));
+            for (int g = 0; g < NG; ++g) {
+                if ((thr[g] >> shift) & 1u) {  // wave-uniform
+                    tb |= need[g];
+                    asm volatile("" : "+v"(tb));  // keeps the branch (no vector select)
+                }
+            }
+        } else {
+#pragma unroll
+            for (int g = 0; g < NG; ++g)
+                tb |= need[g] & (0u - ((thr[g] >> shift) & 1u));
+        }
         const uint32_t ub = r.v[q];
         accepted |= undecided & tb & ~ub;
         undecided &= ~(tb ^ ub);
