@@ -38,16 +38,16 @@ SWEEP_SOURCES = ["paper_2503_14688_amd/csrc/kernels.hip", "paper_2503_14688_amd/
                  "paper_2503_14688_amd/csrc/kernels.hpp"]
 MEASURED_TRAFFIC = {
     # (workload, sweep strategy): bytes per launch
-    ("ising_L1048576_tc", 2): 221.96e9,
-    ("bc_L262144_t16937", 0): 27.75e9,
+    ("ising_L1048576_tc", 2): 221.84e9,
+    ("bc_L262144_t16937", 0): 27.81e9,
 }
-MEASURED_WITH = "998f4ae84e4e7b16"
+MEASURED_WITH = "f967242be360335b"
 # (workload, sweep strategy): wave instructions per 64 words of a colour plane
 # (SQ_INSTS_VALU, SQ_INSTS_SALU) and the clock (GHz, GRBM_GUI_ACTIVE over the
 # dispatch) from the same counter pass
 MEASURED_ISSUE = {
-    ("ising_L1048576_tc", 2): (162.2, 95.9, 2.27),
-    ("bc_L262144_t16937", 0): (367.0, 236.5, 2.39),
+    ("ising_L1048576_tc", 2): (156.6, 95.8, 2.11),
+    ("bc_L262144_t16937", 0): (367.0, 236.5, 2.28),
 }
 
 

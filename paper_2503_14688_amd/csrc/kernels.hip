@@ -163,7 +163,9 @@ __device__ __forceinline__ void ising_em(unsigned long long (&e)[kEmCounters], u
 }
 
 // Q is the calling wavefront's own list.
-template <bool MEASURE, int R, bool UNIFORM, typename List>
+// PLAIN: both Ising groups draw random numbers and neither is never
+// accepted (every finite T > 0), so the classification needs no selects.
+template <bool MEASURE, int R, bool UNIFORM, typename List, bool PLAIN = false>
 __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t c, uint32_t t, const GroupTable &gt,
                                                    uint64_t tile, List &Q, unsigned long long (&e)[kEmCounters])
 {
@@ -223,11 +225,18 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
             const uint32_t a1 = e1 & e2, x1 = e1 ^ e2, a2 = e3 & e4, x2 = e3 ^ e4;
             const uint32_t m4 = a1 & a2;                // a = 4: dE = 8J
             const uint32_t m3 = (a1 & x2) | (a2 & x1);  // a = 3: dE = 4J
-            need[0] = rng3 ? m3 : 0u;
-            need[1] = rng4 ? m4 : 0u;
-            const uint32_t never = (nev3 ? m3 : 0u) | (nev4 ? m4 : 0u);
-            acc = ~(need[0] | need[1] | never);
-            und = need[0] | need[1];
+            if constexpr (PLAIN) {
+                need[0] = m3;
+                need[1] = m4;
+                und = m3 | m4;
+                acc = ~und;
+            } else {
+                need[0] = rng3 ? m3 : 0u;
+                need[1] = rng4 ? m4 : 0u;
+                const uint32_t never = (nev3 ? m3 : 0u) | (nev4 ? m4 : 0u);
+                acc = ~(need[0] | need[1] | never);
+                und = need[0] | need[1];
+            }
             // blocks 0 and 1 for every word: the wavefront would run them
             // anyway unless all 64 of its words were settled, which is rare
             const Block4 b0 = philox_block<UNIFORM>(i, w, t, stream_tag(kPurposeAccept, c, 0), k0, k1);
@@ -738,7 +747,12 @@ __global__ __launch_bounds__(kBlock) void k_sweep_ising(Lattice lat, uint32_t c,
     const uint64_t ntiles = tiles_of<R>(lat);
     if constexpr (variant_compact(V)) {
         __shared__ WaveList<variant_list_cap(V)> Q[kWaves];
-        if (lat.W % kBlock == 0) {
+        using QL = WaveList<variant_list_cap(V)>;
+        const bool plain = (gt.rng_bits & 3u) == 3u && (gt.never_bits & 3u) == 0u;
+        if (lat.W % kBlock == 0 && plain) {
+            for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+                ising_tile_compact<MEASURE, R, true, QL, true>(lat, c, t, gt, tile, Q[threadIdx.x >> 6], e);
+        } else if (lat.W % kBlock == 0) {
             for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
                 ising_tile_compact<MEASURE, R, true>(lat, c, t, gt, tile, Q[threadIdx.x >> 6], e);
         } else {
@@ -823,7 +837,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica 
         if (rep.lat.model == kIsing) {
             if constexpr ((MODELS & kBatchIsing) != 0) {
                 if constexpr (variant_compact(V)) {
-                    if (rep.lat.W % kBlock == 0)
+                    using QL = WaveList<variant_list_cap(V)>;
+                    const bool plain = (gt.rng_bits & 3u) == 3u && (gt.never_bits & 3u) == 0u;
+                    if (rep.lat.W % kBlock == 0 && plain)
+                        ising_tile_compact<false, R, true, QL, true>(rep.lat, c, t, gt, local,
+                                                                     Q[threadIdx.x >> 6].ising, e);
+                    else if (rep.lat.W % kBlock == 0)
                         ising_tile_compact<false, R, true>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].ising, e);
                     else
                         ising_tile_compact<false, R, false>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].ising, e);
