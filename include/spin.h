@@ -19,7 +19,7 @@
  *   Blume-Capel proposes one of the two other states with probability 1/2
  *   each.  Sweeps are counted by t = 0, 1, 2, ...
  * - Randomness (the paper only says its generator works on 32-bit integers,
- *   App. A): Philox4x32-10 with key (seed mod 2^32, seed >> 32) and counter
+ *   App. B): Philox4x32-10 with key (seed mod 2^32, seed >> 32) and counter
  *   (i, w, t, purpose << 16 | c << 8 | blk), w = m >> 5 with m = j >> 1.
  *   Lane b = m & 31 of plane k (k < 32) is bit b of output word k & 3 of the
  *   block blk = k >> 2; the site's 32-bit uniform u has plane 0 as its most

@@ -20,7 +20,9 @@ adds the FP64 observables derived from the integer sums:
 parity pins: see tests/test_oracle_*.py (Philox against rocRAND and the
 Random123 known answers, Ising thresholds against closed forms, brute-force
 Boltzmann histograms, Onsager's energy, Z2, T = 0 / T = inf limits, energy
-bookkeeping, correlation-sum invariants, xi against a closed form).
+bookkeeping, correlation-sum invariants, xi against a closed form, and the
+energy density, magnetisation and C-hat of derive() on constructed lattices
+whose values follow from Eq. 1 and Eq. 2 by hand).
 """
 import ctypes
 import os

@@ -22,7 +22,7 @@
  *                    domain decomposition).  Colour c = (i + j) & 1; colour 0
  *                    is updated first, then colour 1; one sweep = both.
  *   Randomness       the paper says only that its generator works on 32-bit
- *                    integers (App. A).  Here it is Philox4x32-10
+ *                    integers (App. B).  Here it is Philox4x32-10
  *                    (Salmon, Moraes, Dror, Shaw, SC'11) and the bit-plane
  *                    uniform below.
  *   Observables      C(r;t) as the normalised sum over pairs at separation r

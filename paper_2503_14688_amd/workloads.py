@@ -56,7 +56,7 @@ ISING_LARGE = dict(name="ising_L1048576_tc", model=0, L=1 << 20, sweeps=64, T=TC
 ISING_CHECK = dict(name="ising_L4096_tc", model=0, L=1 << 12, sweeps=64, T=TC_ISING, seed=SEED_BASE)
 BC_LARGE = dict(name="bc_L262144_t16937", model=1, L=1 << 18, sweeps=256, T=T_BC_WORKLOAD, seed=SEED_BASE,
                 J=1.0, Delta=0.0)
-BC_CHECK = dict(name="bc_L4096_t16937", model=1, L=1 << 12, sweeps=32, T=T_BC_WORKLOAD, seed=SEED_BASE,
+BC_CHECK = dict(name="bc_L4096_t16937", model=1, L=1 << 12, sweeps=256, T=T_BC_WORKLOAD, seed=SEED_BASE,
                 J=1.0, Delta=0.0)
 
 

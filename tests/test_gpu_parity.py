@@ -252,18 +252,26 @@ def test_uniform_row_tiles_all_strategies(gpu):
     """L = 16384: a plane row is a whole number of 256-word tiles, so the Ising
     sweep takes its row-uniform path (the path of the L = 2^20 workload).
     Every strategy, including the 16-slot list whose overflow words finish in
-    place, reproduces the oracle's trajectory and bond sum."""
+    place, reproduces the oracle's trajectory and bond sum after 3 sweeps and
+    after 64 sweeps at T_c (the depth of the timed workload, where the relaxed
+    lattice sends more words to the work list than near the start)."""
     L, seed = 16384, 2024
-    T = np.full(3, workloads.TC_ISING)
-    s = oracle.init(0, L, seed)
-    oracle.sweep(0, s, seed, 1.0, 0.0, 0, T)
-    bond = oracle.measure(s, [])["bond"]
+    Tc = workloads.TC_ISING
+    s3 = oracle.init(0, L, seed)
+    oracle.sweep(0, s3, seed, 1.0, 0.0, 0, np.full(3, Tc))
+    s64 = s3.copy()
+    oracle.sweep(0, s64, seed, 1.0, 0.0, 3, np.full(61, Tc))
+    bond3, bond64 = oracle.measure(s3, [])["bond"], oracle.measure(s64, [])["bond"]
     for v in range(5):
+        print(f"strategy {v}", flush=True)
         lat = make(gpu, 0, L, seed)
         lat.variant = v
-        lat.sweep(T, fuse_measure=True)
-        assert lat.measure()["bond"] == bond, v
-        assert np.array_equal(lat.spins(), s), v
+        lat.sweep(np.full(3, Tc), fuse_measure=True)
+        assert lat.measure()["bond"] == bond3, v
+        assert np.array_equal(lat.spins(), s3), v
+        lat.sweep(np.full(61, Tc), fuse_measure=True)
+        assert lat.measure()["bond"] == bond64, v
+        assert np.array_equal(lat.spins(), s64), v
         lat.close()
 
 
@@ -282,6 +290,7 @@ def test_ising_L4096_check_run(gpu):
 
 
 def test_blume_capel_L4096_check_run(gpu):
+    """The Blume-Capel check lattice: 2^12 x 2^12 at T = 1.6937, 256 sweeps."""
     w = workloads.BC_CHECK
     L, seed, T = w["L"], w["seed"], w["T"]
     r = workloads.r_sparse(L)
@@ -302,6 +311,7 @@ def sampled_full_size(gpu, model, L, T, n_sweeps, seed, windows, J=1.0, Delta=0.
     lat.sweep(np.full(n_sweeps, T), fuse_measure=True)
     k = 2 * n_sweeps
     for (i0, j0, size) in windows:
+        print(f"window ({i0}, {j0}) of {size} after {n_sweeps} sweeps", flush=True)
         win = oracle.init_window(model, L, seed, i0, j0, size, size)
         oracle.window_sweep(model, win, L, seed, J, Delta, i0, j0, 0, np.full(n_sweeps, T))
         got = lat.window(i0, j0, size, size)
@@ -333,12 +343,16 @@ def test_full_size_ising_sampled(gpu):
     L = workloads.ISING_LARGE["L"]
     if torch.cuda.get_device_properties(0).total_memory < (L * L) // 8 + (8 << 30):
         pytest.skip("needs a GPU with more than 136 GiB")
-    windows = [(0, 0, 40), (L - 20, L - 17, 40), (123457, 987651, 40), (L // 2, 64 * 1000 - 3, 40)]
-    sampled_full_size(gpu, 0, L, workloads.TC_ISING, 2, workloads.SEED_BASE, windows)
+    n = 64  # the timed workload's depth; the exact interior is 4 n sites narrower
+    size = 4 * n + 32
+    windows = [(0, 0, size), (L - 150, L - 170, size), (123457, 987651, size), (L // 2, 64 * 1000 - 3, size)]
+    sampled_full_size(gpu, 0, L, workloads.TC_ISING, n, workloads.SEED_BASE, windows)
 
 
 def test_full_size_blume_capel_sampled(gpu):
-    """Blume-Capel L = 2^18 (16 GiB), sampled windows after 3 sweeps."""
+    """Blume-Capel L = 2^18 (16 GiB), sampled windows after 64 sweeps."""
     L = workloads.BC_LARGE["L"]
-    windows = [(0, 0, 44), (L - 21, 5, 44), (77777, 131071, 44)]
-    sampled_full_size(gpu, 1, L, workloads.T_BC_WORKLOAD, 3, workloads.SEED_BASE, windows)
+    n = 64
+    size = 4 * n + 32
+    windows = [(0, 0, size), (L - 121, 5, size), (77777, 131071, size)]
+    sampled_full_size(gpu, 1, L, workloads.T_BC_WORKLOAD, n, workloads.SEED_BASE, windows)

@@ -47,16 +47,23 @@ def exact_joint_counts(values):
     return g
 
 
-def run_chain(model, L, seed, J, Delta, T, n_sweeps, start=None):
+def run_chain(model, L, seed, J, Delta, T, n_sweeps, start=None, energies=False):
+    """Bond sums and sum s^2 after each sweep; with energies, also the energy
+    density that oracle.derive gives for each state."""
     s = oracle.init(model, L, seed) if start is None else start.copy()
     Bs = np.zeros(n_sweeps, dtype=np.int64)
     Qs = np.zeros(n_sweeps, dtype=np.int64)
+    Es = np.zeros(n_sweeps, dtype=np.float64)
     Tarr = np.array([T])
     for k in range(n_sweeps):
         oracle.sweep(model, s, seed, J, Delta, k, Tarr)
         m = oracle.measure(s, [])
         Bs[k] = m["bond"]
         Qs[k] = m["sum_s2"]
+        if energies:
+            Es[k] = oracle.derive(L, J, Delta, m, [])["e"]
+    if energies:
+        return Bs, Qs, Es
     return Bs, Qs
 
 
@@ -125,8 +132,8 @@ def test_onsager_closed_form_at_tc():
 def test_ising_energy_matches_onsager(T):
     L = 64
     start = np.ones((L, L), dtype=np.int8) if T < TC_ISING else None
-    Bs, _ = run_chain(oracle.ISING, L, 5000 + int(T * 10), 1.0, 0.0, T, 3400, start)
-    e = -Bs[400:].astype(np.float64) / (L * L)
+    _, _, es = run_chain(oracle.ISING, L, 5000 + int(T * 10), 1.0, 0.0, T, 3400, start, energies=True)
+    e = es[400:]
     nb = 30
     per = e.shape[0] // nb
     bm = e[: per * nb].reshape(nb, per).mean(axis=1)
