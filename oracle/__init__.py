@@ -4,9 +4,11 @@ TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
 CPU-baseline leg of the benchmark, never by the product package.  It shares
 no code with the HIP library.
 
-The C part (spin_oracle.c) holds the dynamics, the random stream and the
-brute-force correlation sums; this module wraps it with ctypes and numpy and
-adds the FP64 observables derived from the integer sums:
+The C part holds the dynamics, the random stream and the brute-force
+correlation sums (spin_oracle.c), and the Swendsen-Wang cluster step and the
+Fourier moments of the equilibrium study of App. B (equilibrium_oracle.c);
+this module wraps it with ctypes and numpy and adds the FP64 observables
+derived from the integer sums:
 
   energy density   e = (-J * B + Delta * sum s^2) / L^2, B = Sx(1) + Sy(1)
                    (paper Eq. 3 with the sign of the Hamiltonian, Eq. 1)
@@ -22,7 +24,10 @@ Random123 known answers, Ising thresholds against closed forms, brute-force
 Boltzmann histograms, Onsager's energy, Z2, T = 0 / T = inf limits, energy
 bookkeeping, correlation-sum invariants, xi against a closed form, and the
 energy density, magnetisation and C-hat of derive() on constructed lattices
-whose values follow from Eq. 1 and Eq. 2 by hand).
+whose values follow from Eq. 1 and Eq. 2 by hand; the Swendsen-Wang step
+against connected components from scipy's graph routine at T = 0, isolated
+sites at T = inf and exact Boltzmann histograms; the Fourier moments against
+numpy's FFT).
 """
 import ctypes
 import os
@@ -76,6 +81,14 @@ def _load():
     lib.orc_measure.restype = ctypes.c_int
     lib.orc_schedule.argtypes = [ctypes.c_int, f64p, ctypes.c_uint32, ctypes.c_uint32, f64p]
     lib.orc_schedule.restype = ctypes.c_int
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.orc_sw_threshold.argtypes = [ctypes.c_double, ctypes.c_double, u32p]
+    lib.orc_sw_threshold.restype = ctypes.c_int
+    lib.orc_sw.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_double, i8p,
+                           ctypes.c_uint32, ctypes.c_uint32, f64p, u64p]
+    lib.orc_sw.restype = ctypes.c_int
+    lib.orc_fourier.argtypes = [ctypes.c_int, i8p, f64p]
+    lib.orc_fourier.restype = ctypes.c_int
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
     lib.orc_set_num_threads.argtypes = [ctypes.c_int]
@@ -181,6 +194,36 @@ def schedule(kind, params, t0, n):
     _check(_load().orc_schedule(kind, _ptr(p, ctypes.c_double), t0, n,
                                 _ptr(out, ctypes.c_double)), "schedule")
     return out
+
+
+def sw_threshold(J, T):
+    """(always, thr): the integer Swendsen-Wang bond rule, p = 1 - exp(-2J/T)."""
+    thr = ctypes.c_uint32(0)
+    always = _load().orc_sw_threshold(float(J), float(T), ctypes.byref(thr))
+    return bool(always), int(thr.value)
+
+
+def sw(model, s, seed, J, t0, T, with_labels=False):
+    """len(T) Swendsen-Wang steps (restricted to s = +-1) in place on s; step
+    k uses bath temperature T[k] and sweep index t0 + k.  With with_labels,
+    returns the cluster names (smallest site index) of the last step."""
+    assert s.dtype == np.int8 and s.flags.c_contiguous and s.shape[0] == s.shape[1]
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    lab = np.zeros(s.shape, dtype=np.uint64) if with_labels else None
+    rc = _load().orc_sw(model, s.shape[0], seed, J, _ptr(s, ctypes.c_int8), t0, T.shape[0],
+                        _ptr(T, ctypes.c_double), _ptr(lab, ctypes.c_uint64) if with_labels else None)
+    _check(rc, "sw")
+    return lab
+
+
+def fourier(s):
+    """Fourier moments by the plain double sum: dict(M0, k1, k2) with k1 =
+    M(2 pi / L, 0) (phase along the row index i) and k2 = M(0, 2 pi / L)
+    as complex numbers."""
+    assert s.dtype == np.int8 and s.flags.c_contiguous
+    out = np.zeros(5, dtype=np.float64)
+    _check(_load().orc_fourier(s.shape[0], _ptr(s, ctypes.c_int8), _ptr(out, ctypes.c_double)), "fourier")
+    return {"M0": out[0], "k1": complex(out[1], out[2]), "k2": complex(out[3], out[4])}
 
 
 def num_threads():
