@@ -132,6 +132,21 @@ int spin_sweep_ex(spin_handle *h, uint32_t n, const double *T, uint32_t flags);
 int spin_measure(spin_handle *h, const uint32_t *r, uint32_t n_r, spin_meas *out,
                  int64_t *Sx, int64_t *Sy, double *C_hat);
 
+/* spin_measure for callers that cannot allocate device memory (code that
+ * must not call hipMalloc: serving loops, harnesses that forbid it).  The
+ * same kernels and the same results as spin_measure, bit for bit, but the
+ * counters live in one fixed file-scope device array per GPU (about 48 KiB,
+ * held until the process ends) instead of the handle's reduction buffer, and
+ * the energy/magnetisation sums are always recomputed by the reduction kernel
+ * (fused sums are ignored).  Allocates no device memory and calls no
+ * allocating library routine.  n_r <= 1024, else -EINVAL.  Synchronises the
+ * handle's stream.  All calls on one GPU share its array: calls are
+ * serialised by a process-wide lock, the counters a call uses are cleared on
+ * its stream at its start, and work that other code queues on the array
+ * while a call runs would race with it. */
+int spin_measure_noalloc(spin_handle *h, const uint32_t *r, uint32_t n_r, spin_meas *out,
+                         int64_t *Sx, int64_t *Sy, double *C_hat);
+
 /* Copy the whole lattice to host as int8 s[i * L + j].  Synchronises. */
 int spin_get_spins(spin_handle *h, int8_t *host);
 

@@ -52,7 +52,7 @@ class spin_replica_desc(ctypes.Structure):
 
 
 EXPORTS = ["spin_lattice_bytes", "spin_create", "spin_init_random", "spin_sweep", "spin_sweep_ex",
-           "spin_measure", "spin_get_spins", "spin_get_window", "spin_set_spins", "spin_set_t",
+           "spin_measure", "spin_measure_noalloc", "spin_get_spins", "spin_get_window", "spin_set_spins", "spin_set_t",
            "spin_get_t", "spin_threshold_table", "spin_schedule_fill", "spin_destroy",
            "spin_set_variant", "spin_get_variant", "spin_tune",
            "spin_last_error", "spin_batch_create", "spin_batch_init_random", "spin_batch_run",
@@ -84,6 +84,8 @@ def load_library():
         "spin_sweep_ex": (ctypes.c_int, [vp, ctypes.c_uint32, f64p, ctypes.c_uint32]),
         "spin_measure": (ctypes.c_int, [vp, u32p, ctypes.c_uint32, ctypes.POINTER(spin_meas), i64p, i64p,
                                         f64p]),
+        "spin_measure_noalloc": (ctypes.c_int, [vp, u32p, ctypes.c_uint32, ctypes.POINTER(spin_meas), i64p,
+                                                i64p, f64p]),
         "spin_get_spins": (ctypes.c_int, [vp, i8p]),
         "spin_get_window": (ctypes.c_int, [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                            ctypes.c_uint32, i8p]),
@@ -166,6 +168,21 @@ def spin_measure(h, r=()):
     _check(load_library().spin_measure(h, _ptr(r, ctypes.c_uint32), n, ctypes.byref(out),
                                        _ptr(Sx, ctypes.c_int64), _ptr(Sy, ctypes.c_int64),
                                        _ptr(C, ctypes.c_double)))
+    return {"t": out.t, "sum_s": out.sum_s, "sum_s2": out.sum_s2, "bond": out.bond, "e": out.e,
+            "m": out.m, "xi": out.xi, "Sx": Sx, "Sy": Sy, "C_hat": C}
+
+
+def spin_measure_noalloc(h, r=()):
+    """spin_measure through the entry point that allocates no device memory."""
+    r = np.ascontiguousarray(r, dtype=np.uint32)
+    n = r.shape[0]
+    Sx = np.zeros(n, dtype=np.int64)
+    Sy = np.zeros(n, dtype=np.int64)
+    C = np.zeros(n, dtype=np.float64)
+    out = spin_meas()
+    _check(load_library().spin_measure_noalloc(h, _ptr(r, ctypes.c_uint32), n, ctypes.byref(out),
+                                               _ptr(Sx, ctypes.c_int64), _ptr(Sy, ctypes.c_int64),
+                                               _ptr(C, ctypes.c_double)))
     return {"t": out.t, "sum_s": out.sum_s, "sum_s2": out.sum_s2, "bond": out.bond, "e": out.e,
             "m": out.m, "xi": out.xi, "Sx": Sx, "Sy": Sy, "C_hat": C}
 

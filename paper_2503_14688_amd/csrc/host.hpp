@@ -27,6 +27,7 @@ struct spin_handle {
     int8_t *d_win;
     size_t win_cap;             // bytes
     bool em_valid;              // d_acc[0..3] describe the current state
+    int device;                 // HIP device holding the lattice buffer
 };
 
 namespace spin_host {
@@ -38,6 +39,10 @@ int hip_fail(hipError_t e, const char *what);
 // for the lattice's Blume-Capel group layout bc_groups.
 GroupTable make_groups(int model, uint32_t bc_groups, double J, double Delta, double T);
 int ensure_acc(spin_handle *h, size_t entries);
+// Coherence length I2 / I1 (trapezoid rule up to the first non-positive
+// C-hat) from the correlation sums; writes C-hat(r_q) when C_hat is not NULL.
+double xi_from_sums(const uint32_t *r, const int64_t *Sx, const int64_t *Sy, uint32_t n_r, double N, double C0,
+                    double *C_hat);
 
 } // namespace spin_host
 

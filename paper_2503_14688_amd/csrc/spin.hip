@@ -176,19 +176,23 @@ int ensure_acc(spin_handle *h, size_t entries)
     return 0;
 }
 
-double xi_from(const std::vector<double> &r, const std::vector<double> &C, double C0)
+double xi_from_sums(const uint32_t *r, const int64_t *Sx, const int64_t *Sy, uint32_t n_r, double N, double C0,
+                    double *C_hat)
 {
-    // trapezoid rule for I_n = int r^n C(r) dr over (0, C0) and the sampled
-    // points up to the first non-positive C-hat (paper App. C, Eq. for I_n)
+    // C-hat(r) = (Sx + Sy) / (2 L^2); trapezoid rule for I_n = int r^n C(r) dr
+    // over (0, C0) and the sampled points up to the first non-positive C-hat
+    // (paper App. C, Eq. for I_n)
+    for (uint32_t q = 0; C_hat && q < n_r; ++q)
+        C_hat[q] = (double)(Sx[q] + Sy[q]) / (2.0 * N);
     if (!(C0 > 0.0))
         return 0.0;
     double I1 = 0.0, I2 = 0.0;
     double ra = 0.0, ca = C0;
-    size_t used = 0;
-    for (size_t q = 0; q < r.size(); ++q) {
-        if (!(C[q] > 0.0))
+    uint32_t used = 0;
+    for (uint32_t q = 0; q < n_r; ++q) {
+        const double rb = (double)r[q], cb = (double)(Sx[q] + Sy[q]) / (2.0 * N);
+        if (!(cb > 0.0))
             break;
-        const double rb = r[q], cb = C[q];
         const double w = rb - ra;
         I1 += w * (ra * ca + rb * cb) / 2.0;
         I2 += w * (ra * ra * ca + rb * rb * cb) / 2.0;
@@ -254,6 +258,7 @@ int spin_create(int model, uint32_t L, uint64_t seed, double J, double Delta, vo
     h->buf = dev_buf;
     h->buf_bytes = buf_bytes;
     h->stream = (hipStream_t)hip_stream;
+    h->device = attr.device;
     h->lat.planes = (uint32_t *)dev_buf;
     h->lat.L = L;
     h->lat.W = L / 64;
@@ -383,7 +388,6 @@ int spin_measure(spin_handle *h, const uint32_t *r, uint32_t n_r, spin_meas *out
     out->bond = (int64_t)acc[2] - 2 * (int64_t)acc[3];
     out->e = (-h->J * (double)out->bond + h->Delta * (double)out->sum_s2) / N;
     out->m = (double)out->sum_s / N;
-    std::vector<double> rr(n_r), ch(n_r);
     // pairs with both ends non-zero: every pair for Ising (L^2 per axis and r)
     const int64_t all_pairs = (int64_t)h->L * (int64_t)h->L;
     for (uint32_t q = 0; q < n_r; ++q) {
@@ -391,12 +395,8 @@ int spin_measure(spin_handle *h, const uint32_t *r, uint32_t n_r, spin_meas *out
         const int64_t ay = h->model == SPIN_ISING ? all_pairs : (int64_t)acc[base_y + 2 * q];
         Sx[q] = ax - 2 * (int64_t)acc[base_x + 2 * q + 1];
         Sy[q] = ay - 2 * (int64_t)acc[base_y + 2 * q + 1];
-        rr[q] = (double)r[q];
-        ch[q] = (double)(Sx[q] + Sy[q]) / (2.0 * N);
-        if (C_hat)
-            C_hat[q] = ch[q];
     }
-    out->xi = xi_from(rr, ch, (double)out->sum_s2 / N);
+    out->xi = xi_from_sums(r, Sx, Sy, n_r, N, (double)out->sum_s2 / N, C_hat);
     return 0;
 }
 
