@@ -200,6 +200,49 @@ int spin_destroy(spin_handle *h);
 const char *spin_last_error(void);
 
 /* ------------------------------------------------------------------------
+ * Equilibrium study of the Blume-Capel critical temperature (paper App. B):
+ * Swendsen-Wang cluster updates restricted to the sites with s = +-1,
+ * combined by the caller with Metropolis sweeps into the paper's elementary
+ * Monte Carlo step (10 sweeps, then one Swendsen-Wang step), and the Fourier
+ * moments of the spin field behind the Binder cumulant U4 and the
+ * second-moment correlation length xi_2.
+ * ------------------------------------------------------------------------ */
+
+/* Fourier moments of one configuration, M(k) = sum_x exp(i k.x) s_x with
+ * x = (i, j) (paper App. B, Eq. for M(k)).  Integer sums are exact; the
+ * doubles are summed in IEEE double from the exact row and column sums. */
+typedef struct spin_fourier {
+    uint64_t t;      /* sweep index when measured                              */
+    int64_t sum_s;   /* M(0)                                                    */
+    int64_t sum_s2;  /* sum_x s_x^2                                             */
+    int64_t bond;    /* nearest-neighbour bond sum, as in spin_meas             */
+    double e;        /* energy density, as in spin_meas                         */
+    double re_k1, im_k1;  /* M(2 pi / L, 0): phase 2 pi i / L (row index i)     */
+    double re_k2, im_k2;  /* M(0, 2 pi / L): phase 2 pi j / L (column index j)  */
+} spin_fourier;
+
+/* n Swendsen-Wang steps restricted to the non-zero spins (paper App. B;
+ * Swendsen and Wang 1987): step k at bath temperature T[k] uses sweep index
+ * t + k, then t += n, like n sweeps.  Every bond between two equal non-zero
+ * spins is active iff u < floor(2^32 (1 - exp(-2J / T))) (IEEE double, C
+ * library exp; every such bond when 2^32 (1 - exp(-2J/T)) reaches 2^32, i.e.
+ * T = 0; none at T = +inf), u = word 0 (bond to (i, j+1)) or word 1 (bond to
+ * (i+1, j)) of Philox4x32-10 at counter (i, j, t, 3 << 16); the clusters
+ * (connected components of active bonds, periodic) each flip iff word 0 of
+ * Philox4x32-10 at counter (n, 0, t, 4 << 16) is >= 2^31, n = i L + j being
+ * the cluster's smallest site index.  Vacancies never change.  Asynchronous.
+ * The first call allocates the cluster forest (4 L^2 bytes, released by
+ * spin_destroy).  -EINVAL for L > 32768, a negative or NaN T, or t + n
+ * beyond 2^32; -ENOMEM if the forest cannot be allocated. */
+int spin_sw(spin_handle *h, uint32_t n, const double *T);
+
+/* Fourier moments of the current state (paper App. B), plus the row sums
+ * row_sums[i] = sum_j s(i, j) and column sums col_sums[j] = sum_i s(i, j)
+ * they come from (each may be NULL; otherwise L entries).  Synchronises the
+ * handle's stream; the first call allocates 16 L bytes of device scratch. */
+int spin_measure_fourier(spin_handle *h, spin_fourier *out, int64_t *row_sums, int64_t *col_sums);
+
+/* ------------------------------------------------------------------------
  * Batched replicas: many independent lattices (any mix of model and L), each
  * with its own seed and bath-temperature schedule (paper, Thermal protocols:
  * the quench of protocol 1 and the time-dependent bath of protocol 2),

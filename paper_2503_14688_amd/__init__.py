@@ -36,6 +36,12 @@ class spin_meas(ctypes.Structure):
                 ("xi", ctypes.c_double)]
 
 
+class spin_fourier(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_uint64), ("sum_s", ctypes.c_int64), ("sum_s2", ctypes.c_int64),
+                ("bond", ctypes.c_int64), ("e", ctypes.c_double), ("re_k1", ctypes.c_double),
+                ("im_k1", ctypes.c_double), ("re_k2", ctypes.c_double), ("im_k2", ctypes.c_double)]
+
+
 BATCH_DIRECT = 1
 
 
@@ -54,7 +60,7 @@ class spin_replica_desc(ctypes.Structure):
 EXPORTS = ["spin_lattice_bytes", "spin_create", "spin_init_random", "spin_sweep", "spin_sweep_ex",
            "spin_measure", "spin_measure_noalloc", "spin_get_spins", "spin_get_window", "spin_set_spins", "spin_set_t",
            "spin_get_t", "spin_threshold_table", "spin_schedule_fill", "spin_destroy",
-           "spin_set_variant", "spin_get_variant", "spin_tune",
+           "spin_set_variant", "spin_get_variant", "spin_tune", "spin_sw", "spin_measure_fourier",
            "spin_last_error", "spin_batch_create", "spin_batch_init_random", "spin_batch_run",
            "spin_batch_sync", "spin_batch_replica", "spin_batch_measure", "spin_batch_info",
            "spin_batch_destroy"]
@@ -100,6 +106,8 @@ def load_library():
         "spin_set_variant": (ctypes.c_int, [vp, ctypes.c_int]),
         "spin_get_variant": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int)]),
         "spin_tune": (ctypes.c_int, [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_int)]),
+        "spin_sw": (ctypes.c_int, [vp, ctypes.c_uint32, f64p]),
+        "spin_measure_fourier": (ctypes.c_int, [vp, ctypes.POINTER(spin_fourier), i64p, i64p]),
         "spin_last_error": (ctypes.c_char_p, []),
         "spin_batch_create": (ctypes.c_int, [ctypes.c_uint32, ctypes.POINTER(spin_replica_desc), ctypes.c_uint32,
                                              ctypes.c_uint32, f64p, vp, ctypes.POINTER(vp)]),
@@ -251,6 +259,23 @@ def spin_tune(h, T):
     return v.value
 
 
+def spin_sw(h, T):
+    """len(T) Swendsen-Wang steps restricted to the non-zero spins."""
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    _check(load_library().spin_sw(h, T.shape[0], _ptr(T, ctypes.c_double)))
+
+
+def spin_measure_fourier(h, L):
+    """dict(t, sum_s, sum_s2, bond, e, k1, k2 (complex), row, col)."""
+    out = spin_fourier()
+    row = np.zeros(L, dtype=np.int64)
+    col = np.zeros(L, dtype=np.int64)
+    _check(load_library().spin_measure_fourier(h, ctypes.byref(out), _ptr(row, ctypes.c_int64),
+                                               _ptr(col, ctypes.c_int64)))
+    return {"t": out.t, "sum_s": out.sum_s, "sum_s2": out.sum_s2, "bond": out.bond, "e": out.e,
+            "k1": complex(out.re_k1, out.im_k1), "k2": complex(out.re_k2, out.im_k2), "row": row, "col": col}
+
+
 def spin_last_error():
     return load_library().spin_last_error().decode()
 
@@ -351,6 +376,12 @@ class Lattice:
 
     def tune(self, T):
         return spin_tune(self.h, T)
+
+    def sw(self, T):
+        spin_sw(self.h, T)
+
+    def fourier(self):
+        return spin_measure_fourier(self.h, self.L)
 
     def window(self, i0, j0, rows, cols):
         return spin_get_window(self.h, i0, j0, rows, cols)

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libspin.so")
-SOURCES = ["kernels.hip", "corr.hip", "spin.hip", "batch.hip", "measure_noalloc.hip"]
+SOURCES = ["kernels.hip", "corr.hip", "spin.hip", "batch.hip", "measure_noalloc.hip", "cluster.hip",
+           "equilibrium.hip"]
 ARCH = "gfx950"
 
 

@@ -28,6 +28,8 @@ struct spin_handle {
     size_t win_cap;             // bytes
     bool em_valid;              // d_acc[0..3] describe the current state
     int device;                 // HIP device holding the lattice buffer
+    uint32_t *d_labels;         // Swendsen-Wang cluster forest, L * L entries once used
+    long long *d_lines;         // row and column sums, 2 L entries once used
 };
 
 namespace spin_host {

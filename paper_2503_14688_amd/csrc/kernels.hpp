@@ -92,6 +92,13 @@ bool corr_sparse_y_ok(const Lattice &lat, const uint32_t *r, int n_r);
 hipError_t launch_corr_sparse(const Lattice &lat, bool vertical, int n_r, unsigned long long *acc,
                               hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t st);
+// Equilibrium study (paper App. B): one Swendsen-Wang step at sweep index t
+// with the integer bond rule (thr, always), labels = L * L uint32 scratch;
+// and the row / column sums of the spin field (row[L], col[L]; col zeroed by
+// the caller).
+hipError_t launch_sw_step(const Lattice &lat, uint32_t t, uint32_t thr, bool always, uint32_t *labels,
+                          hipStream_t st);
+hipError_t launch_line_sums(const Lattice &lat, long long *row, long long *col, hipStream_t st);
 hipError_t launch_window(const Lattice &lat, uint32_t i0, uint32_t j0, uint32_t rows, uint32_t cols,
                          int8_t *out, hipStream_t st);
 

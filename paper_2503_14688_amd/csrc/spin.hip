@@ -677,6 +677,10 @@ int spin_destroy(spin_handle *h)
         (void)hipFree(h->d_acc);
     if (h->d_win)
         (void)hipFree(h->d_win);
+    if (h->d_labels)
+        (void)hipFree(h->d_labels);
+    if (h->d_lines)
+        (void)hipFree(h->d_lines);
     delete h;
     return rc;
 }
