@@ -19,11 +19,19 @@ Errors come from jackknife resampling over independent replicas (App. D):
 the cut points are fixed on the full sample and the estimator is recomputed
 on every leave-one-out mean.
 
-Dynamic exponent (App. D, Eq. for log t): log t = z log xi + b over a time
-window, weighted by the error of log t implied by the error of xi
-(d log t / d log xi = z), with jackknife errors.  The correction term
-b' xi^-omega of the paper's fit is left out: the windows used here start
-late enough for it to sit inside the errors, which chi^2/dof shows.
+Dynamic exponent (App. D):
+  from xi      log t = z log xi + b + b' xi^-omega,   omega = 7/4
+               (t is exact, so each point is weighted by the error of xi
+               times the slope of the fitted curve, the effective-variance
+               rule of App. D);
+  from energy  E(t) - E_eq = b t^(-1/z) + b' t^(-2/z) + b'' t^(-(omega+1)/z)
+               (Ising, E_eq = -sqrt 2; nu = 1 so (omega + 1/nu) = omega + 1);
+  joint        one z shared by several such data sets (the paper's Ising xi,
+               Ising energy and Blume-Capel xi), each with its own amplitudes.
+Every fit reports chi^2/dof and the fit quality Q = Gamma_reg(dof/2, chi^2/2)
+(regularised upper incomplete gamma function, App. D); errors are jackknife
+over the independent replicas of each ensemble, added in quadrature across
+independent ensembles.
 """
 import math
 
@@ -175,66 +183,189 @@ def xi_ensemble(r, C_samples, C0_samples):
     return full["xi"], float(jackknife_error(blocks)), full, blocks
 
 
-def fit_z(t, xi, xi_err, xi_blocks=None):
-    """Weighted fit of log t = z log xi + b (App. D) over the given points.
+OMEGA = 1.75  # leading correction-to-scaling exponent of the 2D Ising class (App. D)
 
-    The error of log t is z xi_err / xi (t itself is exact), iterated to the
-    fitted z.  With xi_blocks (n_replicas, len(t)) of leave-one-out xi the
-    fit is repeated per block for the jackknife error of z.
-    Returns dict(z, b, z_err, chi2_dof)."""
+
+def fit_quality(chi2, dof):
+    """Q = Gamma_reg(dof / 2, chi^2 / 2), the probability of a chi^2 at least
+    this large for a correct model (App. D)."""
+    from scipy.special import gammaincc
+    if dof <= 0:
+        return float("nan")
+    return float(gammaincc(0.5 * dof, 0.5 * chi2))
+
+
+def _xi_model(p, xi, correction, omega):
+    z, b = p[0], p[1]
+    y = z * np.log(xi) + b
+    dy = z / xi
+    if correction:
+        y = y + p[2] * xi ** (-omega)
+        dy = dy - omega * p[2] * xi ** (-omega - 1.0)
+    return y, dy
+
+
+def _energy_model(p, t, correction, omega):
+    b, b2, inv_z = p[0], p[1], p[2]
+    y = b * t ** (-inv_z) + b2 * t ** (-2.0 * inv_z)
+    if correction:
+        y = y + p[3] * t ** (-(omega + 1.0) * inv_z)
+    return y
+
+
+def _xi_params(correction):
+    return 3 if correction else 2
+
+
+def _energy_params(correction):
+    return 4 if correction else 3
+
+
+def _residuals_xi(p, t, xi, xi_err, correction, omega):
+    y, dy = _xi_model(p, xi, correction, omega)
+    sigma = np.maximum(1e-40 + xi_err * np.abs(dy), 1e-300)
+    return (np.log(t) - y) / sigma
+
+
+def _residuals_energy(p, t, dE, dE_err, correction, omega):
+    return (dE - _energy_model(p, t, correction, omega)) / dE_err
+
+
+def _start_xi(t, xi, xi_err, correction):
+    """Starting point: the weighted straight line log t = z log xi + b."""
+    X, Y = np.log(xi), np.log(t)
+    w = (xi / np.maximum(xi_err, 1e-300)) ** 2
+    Sw, Sx, Sy = w.sum(), (w * X).sum(), (w * Y).sum()
+    Sxx, Sxy = (w * X * X).sum(), (w * X * Y).sum()
+    z = (Sw * Sxy - Sx * Sy) / (Sw * Sxx - Sx * Sx)
+    b = (Sy - z * Sx) / Sw
+    return [z, b, 0.0] if correction else [z, b]
+
+
+def _start_energy(t, dE, z0, correction):
+    p = [float(dE[0] * t[0] ** (1.0 / z0)), 0.0, 1.0 / z0]
+    return p + [0.0] if correction else p
+
+
+def _solve(fun, p0):
+    from scipy.optimize import least_squares
+    r = least_squares(fun, np.asarray(p0, dtype=np.float64), method="lm", xtol=1e-15, ftol=1e-15, gtol=1e-15,
+                      max_nfev=20000)
+    return r.x, float((r.fun ** 2).sum())
+
+
+def fit_z(t, xi, xi_err, xi_blocks=None, correction=True, omega=OMEGA):
+    """Fit of log t = z log xi + b (+ b' xi^-omega with correction) over the
+    given points, weighted by xi_err times the slope of the curve (App. D).
+    With xi_blocks (n_replicas, len(t)) of leave-one-out xi the fit is
+    repeated per block for the jackknife error of z.
+    Returns dict(z, b, b1 (b' or None), z_err, chi2, dof, chi2_dof, Q)."""
     t = np.asarray(t, dtype=np.float64)
     xi = np.asarray(xi, dtype=np.float64)
     xi_err = np.asarray(xi_err, dtype=np.float64)
-    if t.shape[0] < 3:
-        raise ValueError("need at least three times")
+    k = _xi_params(correction)
+    if t.shape[0] <= k:
+        raise ValueError(f"need more than {k} times")
 
-    def one(x_xi, z_guess=2.0):
-        X, Y = np.log(x_xi), np.log(t)
-        z, b = z_guess, 0.0
-        for _ in range(5):
-            w = 1.0 / np.maximum(z * xi_err / x_xi, 1e-300) ** 2
-            Sw, Sx, Sy = w.sum(), (w * X).sum(), (w * Y).sum()
-            Sxx, Sxy = (w * X * X).sum(), (w * X * Y).sum()
-            z = (Sw * Sxy - Sx * Sy) / (Sw * Sxx - Sx * Sx)
-            b = (Sy - z * Sx) / Sw
-        chi2 = float((w * (Y - z * X - b) ** 2).sum())
-        return z, b, chi2
+    def one(x_xi, p0):
+        return _solve(lambda p: _residuals_xi(p, t, x_xi, xi_err, correction, omega), p0)
 
-    z, b, chi2 = one(xi)
-    out = dict(z=float(z), b=float(b), chi2_dof=chi2 / (t.shape[0] - 2), z_err=None)
+    p, chi2 = one(xi, _start_xi(t, xi, xi_err, correction))
+    dof = t.shape[0] - k
+    out = dict(z=float(p[0]), b=float(p[1]), b1=float(p[2]) if correction else None, chi2=chi2, dof=dof,
+               chi2_dof=chi2 / dof, Q=fit_quality(chi2, dof), z_err=None)
     if xi_blocks is not None:
-        zs = np.array([one(np.asarray(blk, dtype=np.float64), z)[0] for blk in xi_blocks])
+        zs = np.array([one(np.asarray(blk, dtype=np.float64), p)[0][0] for blk in xi_blocks])
         out["z_err"] = float(jackknife_error(zs))
     return out
 
 
-def fit_z_energy(t, dE, dE_err, dE_blocks=None, z0=2.17):
-    """z from the excess energy of the Ising quench to T_c (App. D):
-    E(t) - E_eq = b t^(-1/z) + b' t^(-2/z), E_eq = -sqrt(2) known exactly,
-    fitted by weighted least squares for (b, b', z); with dE_blocks
-    (n_replicas, len(t)) of leave-one-out excess energies the fit is repeated
-    per block for the jackknife error of z.  (The paper adds a third term,
-    b'' t^(-(omega + 1)/z), for its longer times.)
-    Returns dict(z, b, b2, z_err, chi2_dof)."""
-    from scipy.optimize import curve_fit
+def fit_z_energy(t, dE, dE_err, dE_blocks=None, z0=2.17, correction=True, omega=OMEGA):
+    """z from the excess energy of the quench to T_c (App. D):
+    E(t) - E_eq = b t^(-1/z) + b' t^(-2/z) (+ b'' t^(-(omega+1)/z) with
+    correction), weighted least squares for the amplitudes and 1/z; with
+    dE_blocks (n_replicas, len(t)) of leave-one-out excess energies the fit is
+    repeated per block for the jackknife error of z.
+    Returns dict(z, b, b2, b3 (b'' or None), z_err, chi2, dof, chi2_dof, Q)."""
     t = np.asarray(t, dtype=np.float64)
     dE = np.asarray(dE, dtype=np.float64)
     dE_err = np.asarray(dE_err, dtype=np.float64)
-    if t.shape[0] < 4:
-        raise ValueError("need at least four times")
-
-    def model(x, b, b2, inv_z):
-        return b * x ** (-inv_z) + b2 * x ** (-2.0 * inv_z)
+    k = _energy_params(correction)
+    if t.shape[0] <= k:
+        raise ValueError(f"need more than {k} times")
 
     def one(y, p0):
-        p, _ = curve_fit(model, t, y, p0=p0, sigma=dE_err, maxfev=20000)
-        return p
+        return _solve(lambda p: _residuals_energy(p, t, y, dE_err, correction, omega), p0)
 
-    p0 = (float(dE[0] * t[0] ** (1.0 / z0)), 0.0, 1.0 / z0)
-    p = one(dE, p0)
-    chi2 = float((((dE - model(t, *p)) / dE_err) ** 2).sum())
-    out = dict(z=float(1.0 / p[2]), b=float(p[0]), b2=float(p[1]), chi2_dof=chi2 / (t.shape[0] - 3), z_err=None)
+    p, chi2 = one(dE, _start_energy(t, dE, z0, correction))
+    dof = t.shape[0] - k
+    out = dict(z=float(1.0 / p[2]), b=float(p[0]), b2=float(p[1]), b3=float(p[3]) if correction else None,
+               chi2=chi2, dof=dof, chi2_dof=chi2 / dof, Q=fit_quality(chi2, dof), z_err=None)
     if dE_blocks is not None:
-        zs = np.array([1.0 / one(np.asarray(blk, dtype=np.float64), p)[2] for blk in dE_blocks])
+        zs = np.array([1.0 / one(np.asarray(blk, dtype=np.float64), p)[0][2] for blk in dE_blocks])
         out["z_err"] = float(jackknife_error(zs))
+    return out
+
+
+def fit_z_joint(sets, z0=2.17, correction=True, omega=OMEGA):
+    """One z for several data sets (App. D's joint fit: Ising xi, Ising
+    energy, Blume-Capel xi), each with its own amplitudes.
+
+    sets: list of dicts with kind ('xi' or 'energy'), t, y (xi, or E - E_eq),
+    err, and optionally blocks (n_replicas, len(t)) of leave-one-out values
+    and group (name of the replica ensemble the set comes from; sets of one
+    group share replicas).  The jackknife removes one replica of one group
+    at a time from every set of that group; the variances of the groups
+    (independent ensembles) add.
+    Returns dict(z, z_err, chi2, dof, chi2_dof, Q, params (per set))."""
+    prepared = []
+    p0 = [float(z0)]
+    for s in sets:
+        t = np.asarray(s["t"], dtype=np.float64)
+        y = np.asarray(s["y"], dtype=np.float64)
+        e = np.asarray(s["err"], dtype=np.float64)
+        if s["kind"] == "xi":
+            start = _start_xi(t, y, e, correction)[1:]
+        elif s["kind"] == "energy":
+            st = _start_energy(t, y, z0, correction)
+            start = st[:2] + st[3:]
+        else:
+            raise ValueError(f"unknown data set kind {s['kind']!r}")
+        prepared.append((s["kind"], t, e, len(p0), len(start)))
+        p0 += list(start)
+
+    def residuals(p, ys):
+        z = p[0]
+        parts = []
+        for (kind, t, e, off, n), y in zip(prepared, ys):
+            q = p[off:off + n]
+            if kind == "xi":
+                parts.append(_residuals_xi(np.concatenate(([z], q)), t, y, e, correction, omega))
+            else:
+                pe = np.concatenate((q[:2], [1.0 / z], q[2:]))
+                parts.append(_residuals_energy(pe, t, y, e, correction, omega))
+        return np.concatenate(parts)
+
+    ys = [np.asarray(s["y"], dtype=np.float64) for s in sets]
+    p, chi2 = _solve(lambda q: residuals(q, ys), p0)
+    n_points = sum(pr[1].shape[0] for pr in prepared)
+    dof = n_points - len(p0)
+    out = dict(z=float(p[0]), chi2=chi2, dof=dof, chi2_dof=chi2 / dof if dof > 0 else float("nan"),
+               Q=fit_quality(chi2, dof), z_err=None,
+               params=[[float(v) for v in p[off:off + n]] for (_, _, _, off, n) in prepared])
+    groups = {}
+    for k, s in enumerate(sets):
+        if s.get("blocks") is not None:
+            groups.setdefault(s.get("group", k), []).append(k)
+    if groups:
+        var = 0.0
+        for members in groups.values():
+            n_rep = np.asarray(sets[members[0]]["blocks"]).shape[0]
+            zs = []
+            for r in range(n_rep):
+                yb = [np.asarray(sets[k]["blocks"], dtype=np.float64)[r] if k in members else ys[k]
+                      for k in range(len(sets))]
+                zs.append(_solve(lambda q: residuals(q, yb), p)[0][0])
+            var += float(jackknife_error(np.array(zs))) ** 2
+        out["z_err"] = math.sqrt(var)
     return out

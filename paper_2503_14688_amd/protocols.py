@@ -109,6 +109,40 @@ def switch_times(lat, T1, fs, xi_eq, r, t_limit, per_octave=8):
     return {f: crossing_time(ts, xs, f * xi_eq) for f in fs}, done
 
 
+def ensemble_xi_series(data, r, L):
+    """xi(t) by the App. C recipe with jackknife errors, from the per-time
+    ensemble data of quench_batch.  window_ok reports whether the cut points
+    satisfy r* < r_min < r_max < r_cut (the paper adds statistics where they
+    do not)."""
+    from . import analysis
+    out = []
+    for d in data:
+        C = (np.asarray(d["Sx"], dtype=np.float64) + np.asarray(d["Sy"], dtype=np.float64)) / (2.0 * L * L)
+        xi, err, full, _ = analysis.xi_ensemble(r, C, np.asarray(d["sum_s2"], dtype=np.float64) / (float(L) * L))
+        out.append({"t": int(d["t"]), "xi": float(xi), "xi_err": float(err), "window_ok": bool(full["ok"]),
+                    "r_cut": int(full["r_cut"])})
+    return out
+
+
+def switch_times_from_series(series, fs, xi_eq):
+    """t_switch(f) = first crossing of f xi_eq by an ensemble series (points
+    where xi is not defined are left out)."""
+    pts = [(m["t"], m["xi"]) for m in series if m["t"] >= 1 and math.isfinite(m["xi"]) and m["xi"] > 0]
+    ts, xs = [p[0] for p in pts], [p[1] for p in pts]
+    return {f: crossing_time(ts, xs, f * xi_eq) if pts else None for f in fs}
+
+
+def switch_times_ensemble(model, L, seeds, T1, fs, xi_eq, r, t_limit, per_octave=8, J=1.0, Delta=0.0):
+    """t_switch(f) from an ensemble of protocol-1 runs at T1 (one replica per
+    seed, one batch): xi(t) of the replica-averaged C(r) by the App. C
+    recipe, whose cut-off r_cut follows the statistical errors, crossed with
+    f xi_eq(T2) as in switch_times.  Returns ({f: t_switch or None}, series)."""
+    times = [t for t in log_times(t_limit, per_octave) if t >= 1]
+    data = quench_batch(model, L, seeds, T1, times, r, J, Delta)
+    series = ensemble_xi_series(data, r, L)
+    return switch_times_from_series(series, fs, xi_eq), series
+
+
 def two_step_temperatures(T1, T2, t_switch, n):
     """T(t) of protocol 2 for t = 0 .. n - 1 (T1 before t_switch, then T2)."""
     return spin_schedule_fill(SCHEDULE_TWO_STEP, [T1, t_switch, T2], 0, n)

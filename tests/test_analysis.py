@@ -114,3 +114,66 @@ def test_fit_z_energy_two_terms():
     err = reps.std(axis=0, ddof=1) / math.sqrt(48)
     res = analysis.fit_z_energy(t, mean, err, analysis.jackknife_means(reps))
     assert abs(res["z"] - z) < 5 * res["z_err"] and res["z_err"] < 0.1
+
+
+def test_fit_quality_closed_forms():
+    # Gamma_reg(1, x) = exp(-x) and Gamma_reg(2, x) = exp(-x) (1 + x)
+    assert analysis.fit_quality(2.0, 2) == pytest.approx(math.exp(-1.0), rel=1e-14)
+    assert analysis.fit_quality(3.0, 4) == pytest.approx(math.exp(-1.5) * 2.5, rel=1e-14)
+    assert analysis.fit_quality(0.0, 7) == 1.0
+
+
+def test_fit_z_with_the_correction_term():
+    """log t = z log xi + b + b' xi^-omega: exact data give back (z, b, b')
+    and a perfect fit; the plain straight line misses it."""
+    z, b, b1, om = 2.1676, -0.4, 3.0, analysis.OMEGA
+    xi = np.array([3.0, 4.5, 7.0, 11.0, 17.0, 26.0, 40.0, 62.0])
+    t = np.exp(z * np.log(xi) + b + b1 * xi ** (-om))
+    res = analysis.fit_z(t, xi, 0.01 * xi)
+    assert res["z"] == pytest.approx(z, rel=1e-9) and res["b1"] == pytest.approx(b1, rel=1e-7)
+    assert res["chi2_dof"] < 1e-16 and res["Q"] == pytest.approx(1.0, abs=1e-12) and res["dof"] == 5
+    plain = analysis.fit_z(t, xi, 0.01 * xi, correction=False)
+    assert abs(plain["z"] - z) > 1e-3 and plain["chi2_dof"] > 1.0 and plain["Q"] < 0.01
+
+
+def test_fit_z_energy_three_terms():
+    z, b, b2, b3 = 2.1676, 0.31, -0.12, 0.05
+    t = np.array([16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192], dtype=np.float64)
+    dE = b * t ** (-1 / z) + b2 * t ** (-2 / z) + b3 * t ** (-(analysis.OMEGA + 1) / z)
+    res = analysis.fit_z_energy(t, dE, 1e-3 * dE)
+    assert res["z"] == pytest.approx(z, rel=1e-8) and res["b3"] == pytest.approx(b3, rel=1e-5)
+    assert res["dof"] == 6 and res["chi2_dof"] < 1e-16
+
+
+def _joint_sets(rng=None, n_rep=(30, 24)):
+    z, om = 2.1676, analysis.OMEGA
+    xi_i = np.array([3.0, 4.5, 7.0, 11.0, 17.0, 26.0, 40.0, 62.0])
+    t_i = np.exp(z * np.log(xi_i) + 0.2 + 1.5 * xi_i ** (-om))
+    dE = 0.31 * t_i ** (-1 / z) - 0.12 * t_i ** (-2 / z) + 0.05 * t_i ** (-(om + 1) / z)
+    xi_b = np.array([2.5, 4.0, 6.0, 9.5, 15.0, 23.0, 36.0])
+    t_b = np.exp(z * np.log(xi_b) + 0.7 - 0.8 * xi_b ** (-om))
+    exact = [("xi", t_i, xi_i, "ising"), ("energy", t_i, dE, "ising"), ("xi", t_b, xi_b, "bc")]
+    sets = []
+    reps = {}
+    for kind, t, y, group in exact:
+        s = dict(kind=kind, t=t, y=y, err=0.01 * np.abs(y), group=group)
+        if rng is not None:
+            n = n_rep[0] if group == "ising" else n_rep[1]
+            noise = reps.setdefault(group, rng.normal(size=(n, 1)))  # one draw per replica and group
+            r = y[None, :] * (1 + 0.02 * noise + 0.01 * rng.normal(size=(n, y.shape[0])))
+            s.update(y=r.mean(axis=0), err=r.std(axis=0, ddof=1) / math.sqrt(n),
+                     blocks=analysis.jackknife_means(r))
+        sets.append(s)
+    return z, sets
+
+
+def test_joint_fit_shares_z():
+    z, sets = _joint_sets()
+    res = analysis.fit_z_joint(sets)
+    assert res["z"] == pytest.approx(z, rel=1e-8) and res["chi2_dof"] < 1e-14
+    assert res["dof"] == 8 + 8 + 7 - (1 + 2 + 3 + 2)
+    z, sets = _joint_sets(np.random.default_rng(11))
+    res = analysis.fit_z_joint(sets)
+    assert 0 < res["z_err"] < 0.1 and abs(res["z"] - z) < 5 * res["z_err"]
+    single = analysis.fit_z(sets[2]["t"], sets[2]["y"], sets[2]["err"], sets[2]["blocks"])
+    assert res["z_err"] < single["z_err"]  # three data sets pin z better than one

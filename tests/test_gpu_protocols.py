@@ -97,3 +97,81 @@ def test_quench_batch_matches_solo_runs(gpu):
     C = (data[-1]["Sx"] + data[-1]["Sy"]) / (2.0 * L * L)
     xi, err, full, blocks = analysis.xi_ensemble(r, C, data[-1]["sum_s2"] / (L * L))
     assert xi > 0 and err >= 0 and blocks.shape == (4,)
+
+
+def same_series(a, b):
+    """Equal xi series (NaN where xi is undefined counts as equal)."""
+    assert len(a) == len(b)
+    for x, y in zip(a, b):
+        assert x.keys() == y.keys()
+        for k in x:
+            assert x[k] == y[k] or (isinstance(x[k], float) and np.isnan(x[k]) and np.isnan(y[k])), (x, y)
+
+
+def oracle_quench(model, L, seeds, T, times, r):
+    """quench_batch's output computed by plain oracle runs of every seed."""
+    states = [oracle.init(model, L, s) for s in seeds]
+    out, t_now = [], 0
+    for t in times:
+        per = []
+        for s, st in zip(seeds, states):
+            oracle.sweep(model, st, s, 1.0, 0.0, t_now, np.full(t - t_now, T))
+            per.append(oracle.measure(st, r))
+        t_now = t
+        out.append({"t": t, "Sx": np.stack([m["Sx"] for m in per]), "Sy": np.stack([m["Sy"] for m in per]),
+                    "sum_s2": np.array([m["sum_s2"] for m in per], dtype=np.float64),
+                    "e": np.array([oracle.derive(L, 1.0, 0.0, m, r)["e"] for m in per])})
+    return out
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_ensemble_analysis_matches_oracle(gpu, model):
+    """The ensemble path of App. C-D end to end: the batched quench's integer
+    sums equal the oracle's for every replica and time, so xi(t), its
+    jackknife error, the cut points and the fitted z come out identical."""
+    from paper_2503_14688_amd import analysis
+    L, T = 128, workloads.TC_ISING if model == 0 else workloads.TC_BC
+    seeds = [workloads.seed_for(500 + 10 * model + k) for k in range(6)]
+    r = workloads.r_sparse(L)
+    times = [2, 4, 8, 12, 16, 24, 32, 48, 64]
+    got = protocols.quench_batch(model, L, seeds, T, times, r)
+    want = oracle_quench(model, L, seeds, T, times, r)
+    for a, b in zip(got, want):
+        assert a["t"] == b["t"]
+        assert np.array_equal(a["Sx"], b["Sx"]) and np.array_equal(a["Sy"], b["Sy"])
+        assert np.array_equal(a["sum_s2"], b["sum_s2"])
+        assert np.allclose(a["e"], b["e"], rtol=REL, atol=0)
+    sg, sw = protocols.ensemble_xi_series(got, r, L), protocols.ensemble_xi_series(want, r, L)
+    same_series(sg, sw)
+    sel = [k for k, m in enumerate(sg) if m["t"] >= 8]
+    blocks = []
+    for d in got:
+        C = (d["Sx"] + d["Sy"]) / (2.0 * L * L)
+        blocks.append(analysis.xi_ensemble(r, C, d["sum_s2"] / (L * L))[3])
+    blocks = np.array(blocks).T[:, sel]
+    t = np.array([sg[k]["t"] for k in sel], dtype=np.float64)
+    xi = np.array([sg[k]["xi"] for k in sel])
+    err = np.array([sg[k]["xi_err"] for k in sel])
+    fit = analysis.fit_z(t, xi, err, blocks, correction=False)
+    blocks_o = []
+    for d in want:
+        C = (d["Sx"] + d["Sy"]) / (2.0 * L * L)
+        blocks_o.append(analysis.xi_ensemble(r, C, d["sum_s2"] / (L * L))[3])
+    blocks_o = np.array(blocks_o).T[:, sel]
+    fit_o = analysis.fit_z(t, xi, err, blocks_o, correction=False)
+    assert fit == fit_o and 1.0 < fit["z"] < 4.0
+
+
+def test_switch_times_ensemble_match_oracle(gpu):
+    """t_switch from the ensemble estimator (quench at T1 as one batch) equals
+    the same rule applied to the oracle's runs of the same seeds."""
+    L, T1 = 128, 1.66
+    seeds = [workloads.seed_for(700 + k) for k in range(4)]
+    r = workloads.r_sparse(L)
+    fs, xi_eq = (0.4, 0.5, 0.6), 12.0
+    t_gpu, series = protocols.switch_times_ensemble(0, L, seeds, T1, fs, xi_eq, r, t_limit=256, per_octave=4)
+    times = [m["t"] for m in series]
+    want = protocols.ensemble_xi_series(oracle_quench(0, L, seeds, T1, times, r), r, L)
+    same_series(series, want)
+    assert t_gpu == protocols.switch_times_from_series(want, fs, xi_eq)
+    assert all(t_gpu[f] is not None for f in fs)

@@ -129,3 +129,32 @@ def test_series_rejects_times_in_the_past():
     protocols.series(lat, np.full(16, 2.0), [8], workloads.r_sparse(64))
     with pytest.raises(ValueError):
         protocols.series(lat, np.full(16, 2.0), [4], workloads.r_sparse(64))
+
+
+def test_switch_times_from_a_noisy_ensemble():
+    """Replicas of C(r; t) = exp(-r / a(t)) with a(t) = A t^(1/z) and
+    independent noise of 5% per point: the App. C estimator gives xi = 2 a(t)
+    (the exponential's I2 / I1) within its errors, and the crossing of
+    f xi_eq lands on the exact (f xi_eq / 2A)^z within the time resolution
+    that the errors allow; undefined points are skipped."""
+    rng = np.random.default_rng(5)
+    A, z, L = 1.3, 2.17, 4096
+    r = workloads.r_sparse(L)
+    times = [t for t in protocols.log_times(4096, 8) if t >= 1]
+    data = []
+    for t in times:
+        a = A * t ** (1.0 / z)
+        C = np.exp(-r.astype(np.float64)[None, :] / a) * (1 + 0.05 * rng.normal(size=(48, r.shape[0])))
+        N = float(L) * L
+        data.append({"t": t, "Sx": C * N, "Sy": C * N, "sum_s2": np.full(48, N)})
+    series = protocols.ensemble_xi_series(data, r, L)
+    for m in series:
+        if m["t"] >= 16:
+            assert abs(m["xi"] - 2 * A * m["t"] ** (1.0 / z)) < 4 * m["xi_err"] + 0.02 * m["xi"], m
+    xi_eq, fs = 60.0, (0.54, 0.59, 0.64)
+    got = protocols.switch_times_from_series(series, fs, xi_eq)
+    for f in fs:
+        exact = (f * xi_eq / (2 * A)) ** z
+        assert got[f] is not None and abs(got[f] - exact) < 0.05 * exact, (f, got[f], exact)
+    bad = [dict(series[0], xi=float("nan"))] + series[1:]
+    assert protocols.switch_times_from_series(bad, fs, xi_eq) == got
