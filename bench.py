@@ -198,49 +198,68 @@ def run_serving(args, saturated_flips_per_ns):
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in stats.items()}
 
 
-def run_protocol2(args):
-    """The paper's pre-cooling protocol at L = 2^16: one run at T1 locates
-    t_switch(f) for every f from the measured xi(t), then the three two-step
-    runs (same seed, so the same trajectory up to each switch) go to t_max
-    as one batch.  value: all attempted flips of both phases / wall time."""
+def _protocol2(wl):
+    """The paper's pre-cooling protocol for one model: an ensemble of quenches
+    at T1 (one batch) locates t_switch(f) where the App. C coherence length
+    reaches f xi_eq(T2); then the three two-step runs (one seed, so one
+    trajectory up to each switch) run to t_max as one batch.  flips_per_ns:
+    all attempted flips of both phases over the wall time."""
     import torch
-    import paper_2503_14688_amd as spin
     from paper_2503_14688_amd import protocols, workloads
-    wl = workloads.PROTOCOL2_ISING
     L, seed, T1, T2, fs = wl["L"], wl["seed"], wl["T1"], wl["T2"], wl["f"]
     r = workloads.r_sparse(L)
+    seeds = [seed + k for k in range(wl["replicas"])]
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
-    lat = spin.Lattice(wl["model"], L, seed).init_random()
-    lat.variant = lat.tune(T1)
-    t_sw, curve = protocols.switch_times(lat, T1, fs, wl["xi_eq"], r, wl["t_limit"])
-    sweeps_a = lat.t
-    lat.close()
-    del lat
+    t_sw, series = protocols.switch_times_ensemble(wl["model"], L, seeds, T1, fs, wl["xi_eq"], r, wl["t_limit"])
     torch.cuda.synchronize()
     wall_a = time.perf_counter() - wall0
+    sweeps_a = max(m["t"] for m in series)
     if any(t_sw[f] is None for f in fs):
         raise RuntimeError(f"xi did not reach f xi_eq within {wl['t_limit']} sweeps at T1: {t_sw}")
     tsw = [t_sw[f] for f in fs]
-    times = protocols.log_times(wl["t_max"], 4)
+    t_max = wl["t_max"] if wl["t_max"] else max(tsw) + wl["t_after"]
+    times = protocols.log_times(t_max, 4)
     runs = protocols.two_step_batch(wl["model"], L, [seed] * len(fs), T1, T2, tsw, times, r)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    flips = float(L) * L * (sweeps_a + len(fs) * wl["t_max"])
-    log(f"protocol 2: t_switch {tsw} (paper {list(wl['t_switch_paper'])}), {flips / wall / 1e9:.1f} flips/ns")
-    return {"workload": wl["name"], "T1": T1, "T2": T2, "xi_eq_T2": wl["xi_eq"], "f": list(fs),
+    flips = float(L) * L * (len(seeds) * sweeps_a + len(fs) * t_max)
+    log(f"protocol 2 {wl['name']}: t_switch {tsw} (paper {list(wl['t_switch_paper'])}), "
+        f"{flips / wall / 1e9:.1f} flips/ns")
+    pick = [m for m in series if m["t"] in (256, 1024, 4096, 16384, 32768)]
+    return {"workload": wl["name"], "L": L, "T1": T1, "T2": T2, "xi_eq_T2": wl["xi_eq"], "f": list(fs),
             "t_switch": tsw, "t_switch_paper": list(wl["t_switch_paper"]),
-            "xi_at_T1": {str(m["t"]): round(m["xi"], 3) for m in curve if m["t"] in (256, 1024, 4096)},
-            "t_max": wl["t_max"], "sweeps_at_T1": sweeps_a, "wall_s": round(wall, 3),
-            "wall_T1_run_s": round(wall_a, 3), "measurements_at_T1": len(curve),
+            "t_switch_estimator": f"ensemble of {len(seeds)} quenches at T1, App. C xi with jackknife errors",
+            "xi_at_T1": {str(m["t"]): [round(m["xi"], 3), round(m["xi_err"], 3)] for m in pick},
+            "window_ok_fraction": round(float(np.mean([m["window_ok"] for m in series if m["t"] >= 16])), 3),
+            "t_max": t_max, "sweeps_at_T1": sweeps_a, "wall_s": round(wall, 3),
+            "wall_T1_ensemble_s": round(wall_a, 3), "measurements_at_T1": len(series),
             "flips_per_ns": round(flips / wall / 1e9, 2),
             "E_at_t_max": [round(run[-1]["e"], 6) for run in runs],
             "xi_at_t_max": [round(run[-1]["xi"], 2) for run in runs]}
 
 
+def run_protocol2(args):
+    from paper_2503_14688_amd import workloads
+    out = _protocol2(workloads.PROTOCOL2_ISING)
+    try:
+        out["blume_capel"] = _protocol2(workloads.PROTOCOL2_BC)
+    except Exception as exc:  # noqa: BLE001
+        log(f"protocol 2 (Blume-Capel) failed: {exc!r}")
+        out["blume_capel"] = {"error": repr(exc)}
+    return out
+
+
+def _fit_summary(fit, window):
+    return {"z": round(fit["z"], 4), "z_err": round(fit["z_err"], 4) if fit["z_err"] is not None else None,
+            "chi2_dof": round(fit["chi2_dof"], 3), "Q": round(fit["Q"], 3), "t_window": window}
+
+
 def _ensemble_z(wl):
     """One model's ensemble of direct quenches (one batch) with xi(t) by the
-    App. C recipe and z from log t = z log xi + b (App. D), jackknife errors."""
+    App. C recipe and z from Eq. for log t (with and without the b' xi^-omega
+    correction) and, for Ising, from the excess energy (App. D); jackknife
+    errors.  Also returns the data sets for the joint fit."""
     import torch
     from paper_2503_14688_amd import analysis, protocols, workloads
     L, n = wl["L"], wl["replicas"]
@@ -252,77 +271,89 @@ def _ensemble_z(wl):
                                   wl["T"], times, r)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    xi, err, blocks = [], [], []
+    series = protocols.ensemble_xi_series(data, r, L)
+    blocks = []
     for d in data:
         C = (d["Sx"] + d["Sy"]) / (2.0 * L * L)
-        x, e, _, blk = analysis.xi_ensemble(r, C, d["sum_s2"] / (float(L) * L))
-        xi.append(x)
-        err.append(e)
-        blocks.append(blk)
-    xi, err, blocks = np.array(xi), np.array(err), np.array(blocks).T
+        blocks.append(analysis.xi_ensemble(r, C, d["sum_s2"] / (float(L) * L))[3])
+    xi = np.array([m["xi"] for m in series])
+    err = np.array([m["xi_err"] for m in series])
+    blocks = np.array(blocks).T
     sel = np.array([t >= wl["fit_from"] for t in times])
-    fit = analysis.fit_z(np.array(times)[sel], xi[sel], err[sel], blocks[:, sel])
+    t_sel = np.array(times, dtype=np.float64)[sel]
+    window = [wl["fit_from"], wl["t_max"]]
+    fit = analysis.fit_z(t_sel, xi[sel], err[sel], blocks[:, sel])
+    fit_plain = analysis.fit_z(t_sel, xi[sel], err[sel], blocks[:, sel], correction=False)
     flips = float(L) * L * n * wl["t_max"]
     out = {"workload": wl["name"], "replicas": n, "t_max": wl["t_max"], "wall_s": round(wall, 3),
            "flips_per_ns": round(flips / wall / 1e9, 2),
            "xi": {str(t): [round(float(a), 3), round(float(b), 3)] for t, a, b in zip(times, xi, err)
                   if t in (16, 64, 256, 1024, 4096, 8192)},
-           "z_fit": {"z": round(fit["z"], 4), "z_err": round(fit["z_err"], 4),
-                     "chi2_dof": round(fit["chi2_dof"], 3), "t_window": [wl["fit_from"], wl["t_max"]]}}
+           "window_ok": {str(m["t"]): m["window_ok"] for m in series if m["t"] >= wl["fit_from"]},
+           "z_fit": _fit_summary(fit, window), "z_fit_without_correction": _fit_summary(fit_plain, window)}
+    group = wl["name"]
+    sets = [dict(kind="xi", t=t_sel, y=xi[sel], err=err[sel], blocks=blocks[:, sel], group=group)]
     if wl["model"] == 0:
         # excess energy over E_eq(T_c) = -sqrt(2), known exactly for Ising only
         dE = np.array([d["e"] for d in data]).T + math.sqrt(2.0)  # (replicas, times)
-        fit_e = analysis.fit_z_energy(np.array(times)[sel], dE.mean(axis=0)[sel],
-                                      dE.std(axis=0, ddof=1)[sel] / math.sqrt(n),
-                                      analysis.jackknife_means(dE)[:, sel])
-        out["z_fit_energy"] = {"z": round(fit_e["z"], 4), "z_err": round(fit_e["z_err"], 4),
-                               "chi2_dof": round(fit_e["chi2_dof"], 3), "t_window": [wl["fit_from"], wl["t_max"]]}
-    log(f"ensemble {wl['name']}: z = {fit['z']:.4f} +- {fit['z_err']:.4f} (xi)"
+        dE_mean, dE_err = dE.mean(axis=0)[sel], dE.std(axis=0, ddof=1)[sel] / math.sqrt(n)
+        dE_blocks = analysis.jackknife_means(dE)[:, sel]
+        fit_e = analysis.fit_z_energy(t_sel, dE_mean, dE_err, dE_blocks)
+        out["z_fit_energy"] = _fit_summary(fit_e, window)
+        sets.append(dict(kind="energy", t=t_sel, y=dE_mean, err=dE_err, blocks=dE_blocks, group=group))
+    log(f"ensemble {wl['name']}: z = {fit['z']:.4f} +- {fit['z_err']:.4f} (xi, Q = {fit['Q']:.2f})"
         + (f", {out['z_fit_energy']['z']:.4f} +- {out['z_fit_energy']['z_err']:.4f} (energy)"
            if "z_fit_energy" in out else "") + f", {flips / wall / 1e9:.1f} flips/ns")
-    return out
+    return out, sets
 
 
 def run_ensemble(args):
     """Ising and Blume-Capel ensembles at their critical temperatures: the
-    paper's universality check, one z per model (its value: 2.1676(1))."""
-    from paper_2503_14688_amd import workloads
-    out = _ensemble_z(workloads.ENSEMBLE_ISING)
+    paper's universality check, one z per model and the joint fit of Ising
+    xi, Ising energy and Blume-Capel xi (its value: 2.1676(1))."""
+    from paper_2503_14688_amd import analysis, workloads
+    out, sets = _ensemble_z(workloads.ENSEMBLE_ISING)
     out["z_paper"] = 2.1676
-    out["blume_capel"] = _ensemble_z(workloads.ENSEMBLE_BC)
+    out["blume_capel"], bc_sets = _ensemble_z(workloads.ENSEMBLE_BC)
+    joint = analysis.fit_z_joint(sets + bc_sets)
+    out["z_joint"] = {"z": round(joint["z"], 4), "z_err": round(joint["z_err"], 4),
+                      "chi2_dof": round(joint["chi2_dof"], 3), "Q": round(joint["Q"], 3),
+                      "data_sets": "Ising xi + Ising energy + Blume-Capel xi"}
+    log(f"joint z = {joint['z']:.4f} +- {joint['z_err']:.4f} (Q = {joint['Q']:.2f})")
     return out
 
 
-def run(args):
+def single_lattice(wl, steps, warmup, variant=-1):
+    """One lattice of workload wl: T = infinity start, `warmup` untimed sweeps
+    and one measurement, then `steps` timed sweeps with E, M (fused) and C(r)
+    at every sweep count 2^k.  HIP events on the library's stream time each
+    sweep; the roofline entry is the half-sweep kernel's."""
     import torch
     import paper_2503_14688_amd as spin
     from paper_2503_14688_amd import workloads
 
-    wl = {"ising_large": workloads.ISING_LARGE, "bc_large": workloads.BC_LARGE,
-          "ising_check": workloads.ISING_CHECK}[args.workload]
     model, L, T, seed = wl["model"], wl["L"], wl["T"], wl["seed"]
     J, Delta = wl.get("J", 1.0), wl.get("Delta", 0.0)
     r = workloads.r_sparse(L)
-    torch.cuda.init()
     stream = torch.cuda.current_stream()
     lat = spin.Lattice(model, L, seed, J, Delta, stream=stream)
-    strategy = lat.tune(T) if args.variant < 0 else args.variant
+    strategy = lat.tune(T) if variant < 0 else variant
     lat.variant = strategy
     lat.init_random()
     log(f"allocated and initialised {wl['name']} ({lat.buf.numel() / 2**30:.1f} GiB), sweep strategy {strategy}")
     Tk = np.array([T])
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         lat.sweep(Tk)
     lat.measure(r)  # loads every kernel once
     torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} sweeps and one measurement)")
+    log(f"warmup done ({warmup} sweeps and one measurement)")
 
     t_start = lat.t
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
     n_meas = 0
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         t_after = t_start + k + 1
         measure_now = t_after & (t_after - 1) == 0
         ev[2 * k].record(stream)
@@ -334,20 +365,18 @@ def run(args):
             log(f"measured at t = {t_after}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    sweep_ms = sum(ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(args.steps))
-    half_sweep_s = sweep_ms / 1e3 / (2 * args.steps)
-    flips = float(L) * L * args.steps
-    value = flips / (wall * 1e9)
+    sweep_ms = sum(ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(steps))
+    half_sweep_s = sweep_ms / 1e3 / (2 * steps)
+    flips = float(L) * L * steps
     bytes_launch = algorithmic_bytes_per_half_sweep(model, L)
     achieved = bytes_launch / half_sweep_s / 1e9
     traffic = measured_traffic(wl["name"], strategy)
     lat.close()
-
-    out = {
-        "metric": METRIC, "value": round(value, 3), "unit": "flips/ns", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u32 bit-packed spins, u32 Philox4x32-10",
-        "data": "synthetic",
+    del lat
+    torch.cuda.empty_cache()
+    return {
+        "value": round(flips / (wall * 1e9), 3), "wall_s": wall, "steps": steps,
+        "ms_per_step": round(wall * 1e3 / steps, 3),
         "config": {"workload": wl["name"], "model": "ising" if model == 0 else "blume-capel", "L": L,
                    "spins": L * L, "T": T, "J": J, "Delta": Delta, "seed": seed,
                    "measure": f"E, M, C(r) on {len(r)} separations <= {int(r[-1])} at sweeps 2^k",
@@ -362,17 +391,97 @@ def run(args):
                      "avg_launch_ms": round(half_sweep_s * 1e3, 3),
                      "algorithmic_bytes_per_launch": bytes_launch},
     }
-    log(f"timed region done: {value:.1f} flips/ns")
-    del lat
-    torch.cuda.empty_cache()
+
+
+def run_equilibrium(args):
+    """Equilibrium Blume-Capel at Delta = 0 (App. B): independent runs per L
+    (each on its own stream) of EMCS = 10 Metropolis sweeps + 1 Swendsen-Wang
+    step at T_c^BC, U4 and xi_2/L from the Fourier moments, and the
+    reweighted crossings beta_{L,U}, beta_{L,xi2/L} with jackknife errors."""
+    import torch
+    import paper_2503_14688_amd as spin
+    from paper_2503_14688_amd import equilibrium, workloads
+    wl = workloads.EQUILIBRIUM_BC
+    T, beta0 = wl["T"], 1.0 / wl["T"]
+    out = {"workload": wl["name"], "T_sim": T, "Delta": 0.0, "runs_per_L": wl["runs"], "n_therm": wl["n_therm"],
+           "n_emcs": wl["n_emcs"], "emcs": "10 Metropolis sweeps + 1 Swendsen-Wang step",
+           "U4_star": equilibrium.U4_STAR, "xi2_over_L_star": equilibrium.XI_OVER_L_STAR,
+           "T_c_paper": "1.6935583(5)", "sizes": {}}
+    est = {"beta_U": ([], []), "beta_xi": ([], [])}
+    for L in wl["sizes"]:
+        streams = [torch.cuda.Stream() for _ in range(wl["runs"])]
+        lats = [spin.Lattice(wl["model"], L, workloads.seed_for(wl["seed0"] + 1000 * k + L), stream=st).init_random()
+                for k, st in enumerate(streams)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        runs = equilibrium.emcs_runs(lats, T, wl["n_emcs"], wl["every"], wl["n_therm"])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        for lat in lats:
+            lat.close()
+        c = equilibrium.crossings(runs, L, beta0)
+        j = equilibrium.jackknife_observables(runs, L, beta0)
+        n_emcs = wl["runs"] * (wl["n_therm"] + wl["n_emcs"])
+        row = {"U4": [round(j["U4"], 5), round(j.get("U4_err", float("nan")), 5)],
+               "xi2_over_L": [round(j["xi2_over_L"], 5), round(j.get("xi2_over_L_err", float("nan")), 5)],
+               "wall_s": round(wall, 3), "emcs_per_s": round(n_emcs / wall, 1),
+               "flips_per_ns": round(n_emcs * 10.0 * L * L / wall / 1e9, 3)}
+        for key in ("beta_U", "beta_xi"):
+            b, e = c[key], c[key + "_err"]
+            row[key] = [round(b, 6), round(e, 6)] if b is not None and e is not None else None
+            row["T" + key[4:]] = round(1.0 / b, 5) if b is not None else None
+            if b is not None and e is not None:
+                est[key][0].append(b)
+                est[key][1].append(e)
+        out["sizes"][str(L)] = row
+        log(f"equilibrium BC L = {L}: U4 = {j['U4']:.4f}, xi2/L = {j['xi2_over_L']:.4f}, "
+            f"beta_U = {c['beta_U']}, beta_xi = {c['beta_xi']} ({wall:.1f} s)")
+    for key, (vals, errs) in est.items():
+        if vals:
+            m, e, chi = equilibrium.constant_fit(vals, errs)
+            out[key + "_constant_fit"] = {"beta": round(m, 6), "err": round(e, 6), "T_c": round(1.0 / m, 5),
+                                          "chi2_dof": round(chi, 3)}
+    return out
+
+
+def run_bc_large(args):
+    """The Blume-Capel L = 2^18 workload (16 GiB, T = 1.6937, 256 sweeps with
+    E, M and C(r) at sweeps 2^k), timed like the main line."""
+    from paper_2503_14688_amd import workloads
+    wl = workloads.BC_LARGE
+    res = single_lattice(wl, args.bc_steps, 1)
+    res["flips_per_ns"] = res.pop("value")
+    res["wall_s"] = round(res["wall_s"], 3)
+    log(f"{wl['name']}: {res['flips_per_ns']} flips/ns, half-sweep {res['roofline']['avg_launch_ms']} ms")
+    return res
+
+
+def run(args):
+    import torch
+    from paper_2503_14688_amd import workloads
+
+    wl = {"ising_large": workloads.ISING_LARGE, "bc_large": workloads.BC_LARGE,
+          "ising_check": workloads.ISING_CHECK}[args.workload]
+    torch.cuda.init()
+    res = single_lattice(wl, args.steps, args.warmup, args.variant)
+    out = {
+        "metric": METRIC, "value": res["value"], "unit": "flips/ns", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32 bit-packed spins, u32 Philox4x32-10",
+        "data": "synthetic", "config": res["config"],
+        "sweep_only_flips_per_ns": res["sweep_only_flips_per_ns"], "roofline": res["roofline"],
+    }
+    log(f"timed region done: {res['value']:.1f} flips/ns")
     if not args.skip_batched:
         out["batched"] = run_batched(args)
     if not args.skip_serving:
         sat = out["batched"]["flips_per_ns"] if "batched" in out else out["sweep_only_flips_per_ns"]
         out["serving"] = run_serving(args, sat)
     # the extra sections report an error instead of losing the line
-    for name, skip, fn in (("protocol2", args.skip_protocol2, run_protocol2),
-                           ("ensemble", args.skip_ensemble, run_ensemble)):
+    for name, skip, fn in (("blume_capel_large", args.skip_bc or args.workload == "bc_large", run_bc_large),
+                           ("protocol2", args.skip_protocol2, run_protocol2),
+                           ("ensemble", args.skip_ensemble, run_ensemble),
+                           ("equilibrium", args.skip_equilibrium, run_equilibrium)):
         if skip:
             continue
         try:
@@ -412,6 +521,9 @@ def main():
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--skip-protocol2", action="store_true")
     ap.add_argument("--skip-ensemble", action="store_true")
+    ap.add_argument("--skip-bc", action="store_true")
+    ap.add_argument("--skip-equilibrium", action="store_true")
+    ap.add_argument("--bc-steps", type=int, default=256)
     ap.add_argument("--replicas", type=int, default=512)
     ap.add_argument("--batch-sweeps", type=int, default=4096)
     ap.add_argument("--compare-sweeps", type=int, default=256)

@@ -67,9 +67,18 @@ BC_CHECK = dict(name="bc_L4096_t16937", model=1, L=1 << 12, sweeps=256, T=T_BC_W
 # switch times 3746, 4467, 5312 (read as f = 0.54, 0.59, 0.64 in that order:
 # a longer stay at T1 reaches a larger xi).  The benchmark follows each f to
 # t_max = 8192 sweeps (the paper goes to 3,000,000).
+# t_switch(f) comes from an ensemble of `replicas` quenches at T1 (the App. C
+# estimator), measured on a grid of 8 times per octave up to t_limit.
 PROTOCOL2_ISING = dict(name="protocol2_ising_L65536", model=0, L=1 << 16, T1=1.66, T2=2.27414861561203,
                        xi_eq=407.0, f=(0.54, 0.59, 0.64), t_switch_paper=(3746, 4467, 5312), t_max=8192,
-                       t_limit=16384, seed=SEED_BASE)
+                       t_limit=8192, replicas=4, seed=SEED_BASE)
+# The same for Blume-Capel (Delta = 0; Table II): T1 = 1.24, T2 = 1.69661396797728
+# with xi_eq(T2) = 405(2), switch times 34540, 41270, 48599 at L = 2^16.  Run
+# here at L = 2^14 (L / xi_eq = 40) to keep the benchmark within minutes, and
+# each two-step run followed to 4096 sweeps past the latest switch.
+PROTOCOL2_BC = dict(name="protocol2_bc_L16384", model=1, L=1 << 14, T1=1.24, T2=1.69661396797728,
+                    xi_eq=405.0, f=(0.54, 0.59, 0.64), t_switch_paper=(34540, 41270, 48599), t_max=None,
+                    t_after=4096, t_limit=65536, replicas=4, seed=SEED_BASE + 7)
 
 
 # Ensemble of direct quenches for the analysis of App. C and D: 64 Ising
@@ -81,6 +90,16 @@ ENSEMBLE_ISING = dict(name="ensemble_ising_L4096_tc", model=0, L=1 << 12, replic
 # universality claim is one z for both models.
 ENSEMBLE_BC = dict(name="ensemble_bc_L4096_tc", model=1, L=1 << 12, replicas=64, T=TC_BC,
                    t_max=8192, per_octave=2, fit_from=256, seed0=2000)
+
+
+# Equilibrium finite-size study of the Blume-Capel critical temperature
+# (App. B): Delta = 0, independent runs from the T = infinity start at the
+# paper's T_c, elementary Monte Carlo step = 10 Metropolis sweeps + one
+# Swendsen-Wang step, 40 EMCS of thermalisation (the paper's equilibration
+# time at L = 4096), then a measurement after every EMCS (the paper: L up to
+# 4096, 100 runs of 4 x 10^5 EMCS each).
+EQUILIBRIUM_BC = dict(name="equilibrium_bc_tc", model=1, sizes=(64, 128, 256), runs=8, n_therm=40,
+                      n_emcs=1000, every=1, T=TC_BC, seed0=3000)
 
 
 def batched_replicas(n=512, sizes=(256, 512, 1024, 2048), taus=(64.0, 256.0, 1024.0)):
