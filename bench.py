@@ -192,6 +192,15 @@ def run_serving(args, saturated_flips_per_ns):
     stats = srv.run(jobs)
     log(f"serving: {stats['jobs']} jobs in {stats['wall_s']:.2f} s, p50 {stats['latency_p50_s']:.3f} s, "
         f"p99 {stats['latency_p99_s']:.3f} s")
+    # capacity: the same jobs all queued at once (offered load above one), so
+    # the device never waits for arrivals
+    jobs = [Job(**d) for d in workloads.serving_jobs(args.jobs, rate)]
+    cap = Server(epoch=64).run(jobs, realtime=False)
+    log(f"serving at capacity: {cap['jobs']} jobs in {cap['wall_s']:.2f} s, {cap['flips_per_ns']:.0f} flips/ns")
+    stats["capacity"] = {"jobs_per_s": round(cap["jobs_per_s"], 3), "flips_per_ns": round(cap["flips_per_ns"], 1),
+                         "fraction_of_batched_engine": round(cap["flips_per_ns"] / saturated_flips_per_ns, 3),
+                         "latency_p50_s": round(cap["latency_p50_s"], 3), "batches_built": cap["batches_built"],
+                         "note": "all jobs queued at t = 0"}
     stats.update({"arrival_rate_per_s": round(rate, 3), "offered_load": 0.8,
                   "workload": "Poisson arrivals, L = 2^U (U uniform 8..14), sweeps 2^V (V uniform 10..14), "
                               "Ising or Blume-Capel at T_c, admitted by slots and 80% of free HBM"})
@@ -401,7 +410,11 @@ def run_equilibrium(args):
     import torch
     import paper_2503_14688_amd as spin
     from paper_2503_14688_amd import equilibrium, workloads
-    wl = workloads.EQUILIBRIUM_BC
+    wl = dict(workloads.EQUILIBRIUM_BC)
+    if getattr(args, "equilibrium_sizes", None):
+        wl["sizes"] = tuple(int(x) for x in args.equilibrium_sizes.split(","))
+    if getattr(args, "equilibrium_emcs", None):
+        wl["n_emcs"] = args.equilibrium_emcs
     T, beta0 = wl["T"], 1.0 / wl["T"]
     out = {"workload": wl["name"], "T_sim": T, "Delta": 0.0, "runs_per_L": wl["runs"], "n_therm": wl["n_therm"],
            "n_emcs": wl["n_emcs"], "emcs": "10 Metropolis sweeps + 1 Swendsen-Wang step",
@@ -509,6 +522,10 @@ def calibrate_copy(gib=8):
           flush=True)
 
 
+SECTIONS = {"batched": run_batched, "blume_capel_large": run_bc_large, "protocol2": run_protocol2,
+            "ensemble": run_ensemble, "equilibrium": run_equilibrium}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -531,9 +548,20 @@ def main():
     ap.add_argument("--variant", type=int, default=-1, help="sweep strategy (default: tuned)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 8 GiB device copy (traffic-counter calibration)")
+    ap.add_argument("--section", choices=sorted(SECTIONS),
+                    help="run only this section and print its JSON (profiling runs; not the benchmark line)")
+    ap.add_argument("--equilibrium-sizes", type=str, default=None,
+                    help="comma-separated L of the equilibrium section (default: the workload's)")
+    ap.add_argument("--equilibrium-emcs", type=int, default=None,
+                    help="measured EMCS per run of the equilibrium section (default: the workload's)")
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.section:
+        import torch
+        torch.cuda.init()
+        print(json.dumps({args.section: SECTIONS[args.section](args)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab decomposition "

@@ -296,14 +296,19 @@ int spin_batch_run(spin_batch *b, uint32_t n, uint32_t flags);
 /* Wait for the batch's queued work. */
 int spin_batch_sync(spin_batch *b);
 
-/* Borrow replica k's handle (measure, get/set spins); owned by the batch. */
+/* Borrow replica k's handle (measure, get/set spins); owned by the batch.
+ * spin_sweep, spin_sweep_ex, spin_sw and spin_set_t on a borrowed handle
+ * return -EINVAL: only spin_batch_run advances a replica, so no sweep index
+ * (and no random number) is ever used twice. */
 int spin_batch_replica(spin_batch *b, uint32_t k, spin_handle **out);
 
 /* Measure every replica's current state, as spin_measure on each replica's
  * handle (paper Eqs. 2-3 and App. C): out[k] for replica k, Sx[k * n_r + q]
  * and Sy[k * n_r + q] for separation r[q] (caller-owned host arrays of n and
  * n * n_r entries; Sx, Sy may be NULL when n_r == 0).  Every r[q] must lie in
- * 0 < r < L of every replica.  Synchronises the batch's stream. */
+ * 0 < r < L of every replica.  The kernels of all replicas are queued on the
+ * batch's stream into one counter buffer (allocated at the first call, kept
+ * by the batch), copied back once; synchronises the batch's stream once. */
 int spin_batch_measure(spin_batch *b, const uint32_t *r, uint32_t n_r, spin_meas *out, int64_t *Sx,
                        int64_t *Sy);
 

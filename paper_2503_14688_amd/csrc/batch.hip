@@ -2,7 +2,8 @@
 // size and model, each following its own bath-temperature schedule (paper,
 // Thermal protocols), advanced together by one launch per half-sweep over a
 // flat list of all replicas' tiles.  A run of n sweeps is captured once as a
-// HIP graph of 2n launches and replayed; the sweep strategy (rows per thread,
+// HIP graph of 2n launches (plus one that advances the device step counter)
+// and replayed for every later run of n sweeps; the sweep strategy (rows per thread,
 // per-word or compacting lazy test) is chosen by timing every strategy on
 // scratch copies of the lattices.
 #include "host.hpp"
@@ -32,8 +33,13 @@ struct spin_batch {
     uint32_t *d_tile_rep[2] = {nullptr, nullptr};
     uint64_t ntiles[2] = {0, 0};
     GroupTable *d_tables = nullptr;
+    unsigned long long *d_meas = nullptr;  // measurement counters of every replica
+    size_t meas_cap = 0;                   // entries
+    uint32_t *d_step = nullptr;          // schedule step on the device (= t between runs)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    uint32_t graph_n = 0;                // run length and strategy the graph was captured for
+    int graph_variant = -1;
 };
 
 namespace {
@@ -59,6 +65,10 @@ void release(spin_batch *b)
     }
     if (b->d_tables)
         (void)hipFree(b->d_tables);
+    if (b->d_meas)
+        (void)hipFree(b->d_meas);
+    if (b->d_step)
+        (void)hipFree(b->d_step);
     for (spin_handle *h : b->reps)
         spin_destroy(h);
     if (b->own_stream && b->stream)
@@ -102,16 +112,20 @@ int build_tiles(spin_batch *b, int rows)
     return 0;
 }
 
-int launch_sweeps(spin_batch *b, int variant, uint64_t t0, uint32_t n, hipStream_t st)
+// n sweeps at schedule steps *d_step + 0 .. n - 1; with advance, the device
+// step counter moves on by n afterwards (a run), without it every sweep is
+// repeated at the current step (tuning).
+int launch_sweeps(spin_batch *b, int variant, uint32_t n, bool advance, hipStream_t st)
 {
     const int k = shape_of(variant);
     for (uint32_t q = 0; q < n; ++q) {
-        const uint64_t step = t0 + q;
         for (uint32_t c = 0; c < 2; ++c)
-            HIP_TRY(spin::launch_batch_half_sweep(variant, b->models, b->d_reps[k], b->d_tile_rep[k],
-                                                  b->ntiles[k], b->d_tables, b->n_steps, (uint32_t)step, c, st),
+            HIP_TRY(spin::launch_batch_half_sweep(variant, b->models, b->d_reps[k], b->d_tile_rep[k], b->ntiles[k],
+                                                  b->d_tables, b->n_steps, b->d_step, advance ? q : 0u, c, st),
                     "batched sweep launch");
     }
+    if (advance)
+        HIP_TRY(spin::launch_advance_step(b->d_step, n, st), "step counter launch");
     return 0;
 }
 
@@ -171,12 +185,12 @@ int autotune(spin_batch *b)
         // the current schedule step is the only one known to exist: every
         // tuning sweep uses it
         for (int w = 0; w < 8 && rc == 0; ++w)
-            rc = launch_sweeps(b, 0, b->t, 1, b->stream);
+            rc = launch_sweeps(b, 0, 1, false, b->stream);
         for (int round = 0; round < 3 && rc == 0 && e == hipSuccess; ++round) {
             for (int v = 0; v < spin::kVariants && rc == 0 && e == hipSuccess; ++v) {
                 if ((e = hipEventRecord(e0, b->stream)) != hipSuccess)
                     break;
-                rc = launch_sweeps(b, v, b->t, 2, b->stream);
+                rc = launch_sweeps(b, v, 2, false, b->stream);
                 if (rc)
                     break;
                 float ms = 0.0f;
@@ -261,6 +275,7 @@ int spin_batch_create(uint32_t n, const spin_replica_desc *descs, uint32_t n_sch
             return fail(rc, "replica %u: %s", r, msg.c_str());
         }
         h->t = d.t0;
+        h->batch_owned = true;
         b->models |= d.model == SPIN_ISING ? spin::kBatchIsing : spin::kBatchBc;
         b->reps.push_back(h);
         b->t0.push_back(d.t0);
@@ -294,6 +309,15 @@ int spin_batch_create(uint32_t n, const spin_replica_desc *descs, uint32_t n_sch
     if (e != hipSuccess) {
         release(b);
         return hip_fail(e, "threshold tables");
+    }
+    e = hipMalloc(&b->d_step, sizeof(uint32_t));
+    if (e == hipSuccess) {
+        const uint32_t zero = 0;
+        e = hipMemcpy(b->d_step, &zero, sizeof zero, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        release(b);
+        return hip_fail(e, "step counter");
     }
     for (int rows : {4, 8}) {
         int rc = build_tiles(b, rows);
@@ -335,8 +359,12 @@ int spin_batch_run(spin_batch *b, uint32_t n, uint32_t flags)
             return rc;
     }
     if (flags & SPIN_BATCH_DIRECT) {
-        if (int rc = launch_sweeps(b, b->variant, b->t, n, b->stream))
+        if (int rc = launch_sweeps(b, b->variant, n, true, b->stream))
             return rc;
+    } else if (b->exec && b->graph_n == n && b->graph_variant == b->variant) {
+        // the same run length again: the captured launches read their steps
+        // from the device counter, so the graph replays as it is
+        HIP_TRY(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
     } else {
         HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
         if (b->exec) {
@@ -347,8 +375,10 @@ int spin_batch_run(spin_batch *b, uint32_t n, uint32_t flags)
             (void)hipGraphDestroy(b->graph);
             b->graph = nullptr;
         }
+        b->graph_n = 0;
+        b->graph_variant = -1;
         HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-        int rc = launch_sweeps(b, b->variant, b->t, n, b->stream);
+        int rc = launch_sweeps(b, b->variant, n, true, b->stream);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(b->stream, &g);
         if (rc) {
@@ -360,6 +390,8 @@ int spin_batch_run(spin_batch *b, uint32_t n, uint32_t flags)
             return hip_fail(e, "hipStreamEndCapture");
         b->graph = g;
         HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        b->graph_n = n;
+        b->graph_variant = b->variant;
         HIP_TRY(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
     }
     b->t += n;
@@ -390,17 +422,48 @@ int spin_batch_measure(spin_batch *b, const uint32_t *r, uint32_t n_r, spin_meas
 {
     if (!b || !out || (n_r && (!r || !Sx || !Sy)))
         return fail(-EINVAL, "bad batch or NULL output");
+    for (uint32_t q = 1; q < n_r; ++q)
+        if (r[q] <= r[q - 1])
+            return fail(-EINVAL, "separations must be strictly increasing");
     for (size_t k = 0; k < b->reps.size(); ++k) {
         const uint32_t L = b->reps[k]->L;
         for (uint32_t q = 0; q < n_r; ++q)
             if (r[q] == 0 || r[q] >= L)
                 return fail(-EINVAL, "separation %u outside 0 < r < L = %u of replica %zu", r[q], L, k);
     }
+    // every replica's counters in one buffer: one fill, the reduction and
+    // correlation kernels of each replica queued back to back, one copy, one
+    // synchronisation
+    const size_t per = measure_counters(n_r), total = per * b->reps.size();
+    if (total > b->meas_cap) {
+        HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+        if (b->d_meas)
+            (void)hipFree(b->d_meas);
+        b->d_meas = nullptr;
+        b->meas_cap = 0;
+        hipError_t e = hipMalloc(&b->d_meas, total * sizeof(unsigned long long));
+        if (e != hipSuccess) {
+            b->d_meas = nullptr;
+            return fail(-ENOMEM, "measurement counters (%zu): %s", total, hipGetErrorString(e));
+        }
+        b->meas_cap = total;
+    }
+    HIP_TRY(spin::launch_fill_u64(b->d_meas, total, 0ull, b->stream), "fill kernel launch");
+    for (size_t k = 0; k < b->reps.size(); ++k) {
+        unsigned long long *acc = b->d_meas + k * per;
+        HIP_TRY(spin::launch_measure_em(b->reps[k]->lat, acc, b->stream), "measure kernel launch");
+        if (n_r > 0)
+            if (int rc = queue_correlations(b->reps[k]->lat, r, n_r, acc, b->stream))
+                return rc;
+    }
+    std::vector<unsigned long long> acc(total);
+    HIP_TRY(hipMemcpyAsync(acc.data(), b->d_meas, total * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           b->stream),
+            "hipMemcpyAsync");
     HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
     for (size_t k = 0; k < b->reps.size(); ++k)
-        if (int rc = spin_measure(b->reps[k], r, n_r, out + k, n_r ? Sx + k * n_r : nullptr,
-                                  n_r ? Sy + k * n_r : nullptr, nullptr))
-            return rc;
+        finish_measure(b->reps[k], acc.data() + k * per, r, n_r, out + k, n_r ? Sx + k * n_r : nullptr,
+                       n_r ? Sy + k * n_r : nullptr, nullptr);
     return 0;
 }
 

@@ -43,6 +43,8 @@ int spin_sw(spin_handle *h, uint32_t n, const double *T)
         return fail(-EINVAL, "NULL handle");
     if (n > 0 && !T)
         return fail(-EINVAL, "NULL temperature array");
+    if (h->batch_owned)
+        return fail(-EINVAL, "the handle belongs to a batch: advance it with spin_batch_run");
     if (h->L > kMaxSwL)
         return fail(-EINVAL, "Swendsen-Wang steps need L <= %u (got %u)", kMaxSwL, h->L);
     if (h->t + n > (1ull << 32))

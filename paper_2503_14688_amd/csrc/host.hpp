@@ -30,6 +30,7 @@ struct spin_handle {
     int device;                 // HIP device holding the lattice buffer
     uint32_t *d_labels;         // Swendsen-Wang cluster forest, L * L entries once used
     long long *d_lines;         // row and column sums, 2 L entries once used
+    bool batch_owned;           // advanced only through its batch (spin_batch_run)
 };
 
 namespace spin_host {
@@ -41,6 +42,15 @@ int hip_fail(hipError_t e, const char *what);
 // for the lattice's Blume-Capel group layout bc_groups.
 GroupTable make_groups(int model, uint32_t bc_groups, double J, double Delta, double T);
 int ensure_acc(spin_handle *h, size_t entries);
+// Measurement in two halves: queue the correlation kernels of n_r
+// separations into acc (laid out as spin_measure's counters: 4 energy /
+// magnetisation counters, then 2 per separation for x, then for y), and
+// turn copied-back counters into the results.
+size_t measure_counters(uint32_t n_r);
+int queue_correlations(const spin::Lattice &lat, const uint32_t *r, uint32_t n_r, unsigned long long *acc,
+                       hipStream_t st);
+void finish_measure(const spin_handle *h, const unsigned long long *acc, const uint32_t *r, uint32_t n_r,
+                    spin_meas *out, int64_t *Sx, int64_t *Sy, double *C_hat);
 // Coherence length I2 / I1 (trapezoid rule up to the first non-positive
 // C-hat) from the correlation sums; writes C-hat(r_q) when C_hat is not NULL.
 double xi_from_sums(const uint32_t *r, const int64_t *Sx, const int64_t *Sy, uint32_t n_r, double N, double C0,

@@ -819,9 +819,14 @@ template <int V, int MODELS>
 __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica *__restrict__ reps,
                                                              const uint32_t *__restrict__ tile_rep, uint64_t ntiles,
                                                              const GroupTable *__restrict__ tables, uint32_t stride,
-                                                             uint32_t step, uint32_t c)
+                                                             const uint32_t *__restrict__ step_base, uint32_t step_off,
+                                                             uint32_t c)
 {
     constexpr int R = variant_rows(V);
+    // schedule step: the batch's device step counter (advanced at the end of
+    // every run) plus this launch's offset in the run, so that a captured
+    // run can be replayed for the next steps unchanged
+    const uint32_t step = __builtin_amdgcn_readfirstlane(*step_base) + step_off;
     __shared__ std::conditional_t<variant_compact(V), BatchList<V, MODELS>, int> Q[kWaves];
     unsigned long long e[kEmCounters] = {0, 0, 0, 0};
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -994,6 +999,12 @@ __global__ __launch_bounds__(kBlock) void k_corr(Lattice lat, RList rl, int n_r,
 
 // ------------------------------------------------------------- helpers --
 
+__global__ void k_advance_step(uint32_t *step, uint32_t n)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *step += n;
+}
+
 __global__ void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v)
 {
     for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n;
@@ -1093,7 +1104,8 @@ uint64_t sweep_tiles(const Lattice &lat, int rows)
 
 template <int V, int MODELS>
 hipError_t launch_batch_vm(const BatchReplica *reps, const uint32_t *tile_rep, uint64_t ntiles,
-                           const GroupTable *tables, uint32_t stride, uint32_t step, uint32_t colour, hipStream_t st)
+                           const GroupTable *tables, uint32_t stride, const uint32_t *step_base, uint32_t step,
+                           uint32_t colour, hipStream_t st)
 {
     // The single-lattice launch's grid: up to 65536 blocks, a block walks
     // tiles by grid stride.  (A grid of only the resident blocks, each walking
@@ -1102,32 +1114,33 @@ hipError_t launch_batch_vm(const BatchReplica *reps, const uint32_t *tile_rep, u
     // better than a persistent block does.)
     constexpr unsigned g = 65536u;
     hipLaunchKernelGGL((k_batch_half_sweep<V, MODELS>), dim3(g < ntiles ? g : (unsigned)ntiles), dim3(kBlock), 0,
-                       st, reps, tile_rep, ntiles, tables, stride, step, colour);
+                       st, reps, tile_rep, ntiles, tables, stride, step_base, step, colour);
     return hipGetLastError();
 }
 
 template <int V>
 hipError_t launch_batch_v(int models, const BatchReplica *reps, const uint32_t *tile_rep, uint64_t ntiles,
-                          const GroupTable *tables, uint32_t stride, uint32_t step, uint32_t colour, hipStream_t st)
+                          const GroupTable *tables, uint32_t stride, const uint32_t *step_base, uint32_t step,
+                          uint32_t colour, hipStream_t st)
 {
     switch (models) {
-    case kBatchIsing: return launch_batch_vm<V, kBatchIsing>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
-    case kBatchBc: return launch_batch_vm<V, kBatchBc>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
-    case kBatchMixed: return launch_batch_vm<V, kBatchMixed>(reps, tile_rep, ntiles, tables, stride, step, colour, st);
+    case kBatchIsing: return launch_batch_vm<V, kBatchIsing>(reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
+    case kBatchBc: return launch_batch_vm<V, kBatchBc>(reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
+    case kBatchMixed: return launch_batch_vm<V, kBatchMixed>(reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_batch_half_sweep(int variant, int models, const BatchReplica *reps, const uint32_t *tile_rep,
-                                   uint64_t ntiles, const GroupTable *tables, uint32_t stride, uint32_t step,
-                                   uint32_t colour, hipStream_t st)
+                                   uint64_t ntiles, const GroupTable *tables, uint32_t stride,
+                                   const uint32_t *step_base, uint32_t step, uint32_t colour, hipStream_t st)
 {
     switch (variant) {
-    case 0: return launch_batch_v<0>(models, reps, tile_rep, ntiles, tables, stride, step, colour, st);
-    case 1: return launch_batch_v<1>(models, reps, tile_rep, ntiles, tables, stride, step, colour, st);
-    case 2: return launch_batch_v<2>(models, reps, tile_rep, ntiles, tables, stride, step, colour, st);
-    case 3: return launch_batch_v<3>(models, reps, tile_rep, ntiles, tables, stride, step, colour, st);
-    case 4: return launch_batch_v<4>(models, reps, tile_rep, ntiles, tables, stride, step, colour, st);
+    case 0: return launch_batch_v<0>(models, reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
+    case 1: return launch_batch_v<1>(models, reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
+    case 2: return launch_batch_v<2>(models, reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
+    case 3: return launch_batch_v<3>(models, reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
+    case 4: return launch_batch_v<4>(models, reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1162,6 +1175,12 @@ hipError_t launch_corr(const Lattice &lat, bool vertical, const uint32_t *r, int
         else
             hipLaunchKernelGGL((k_corr<kBlumeCapel, false>), grid, block, 0, st, lat, rl, n_r, acc);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_step(uint32_t *step, uint32_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(64), 0, st, step, n);
     return hipGetLastError();
 }
 

@@ -73,9 +73,12 @@ uint64_t sweep_tiles(const Lattice &lat, int rows);
 // Models present in a batch (bit 0 Ising, bit 1 Blume-Capel): the batched
 // kernel is specialised on it.
 enum BatchModels : int { kBatchIsing = 1, kBatchBc = 2, kBatchMixed = 3 };
+// The schedule step of a launch is *step_base + step (step_base: the batch's
+// device step counter, which launch_advance_step moves on by n after a run).
 hipError_t launch_batch_half_sweep(int variant, int models, const BatchReplica *reps, const uint32_t *tile_rep,
-                                   uint64_t ntiles, const GroupTable *tables, uint32_t stride, uint32_t step,
-                                   uint32_t colour, hipStream_t st);
+                                   uint64_t ntiles, const GroupTable *tables, uint32_t stride,
+                                   const uint32_t *step_base, uint32_t step, uint32_t colour, hipStream_t st);
+hipError_t launch_advance_step(uint32_t *step, uint32_t n, hipStream_t st);
 hipError_t launch_half_sweep(const Lattice &lat, uint32_t colour, uint32_t t, const GroupTable &gt,
                              unsigned long long *em_acc, hipStream_t st);
 hipError_t launch_measure_em(const Lattice &lat, unsigned long long *em_acc, hipStream_t st);

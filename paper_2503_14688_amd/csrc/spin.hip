@@ -205,6 +205,50 @@ double xi_from_sums(const uint32_t *r, const int64_t *Sx, const int64_t *Sy, uin
     return I2 / I1;
 }
 
+size_t measure_counters(uint32_t n_r) { return spin::kEmCounters + 4 * (size_t)n_r; }
+
+int queue_correlations(const spin::Lattice &lat, const uint32_t *r, uint32_t n_r, unsigned long long *acc,
+                       hipStream_t st)
+{
+    const size_t base_x = spin::kEmCounters, base_y = base_x + 2 * (size_t)n_r;
+    for (int axis = 0; axis < 2; ++axis) {
+        const bool vertical = axis == 1;
+        unsigned long long *dst = acc + (vertical ? base_y : base_x);
+        const bool fast = vertical ? spin::corr_sparse_y_ok(lat, r, (int)n_r) : spin::corr_sparse_x_ok(lat, r, (int)n_r);
+        if (fast) {
+            HIP_TRY(spin::launch_corr_sparse(lat, vertical, (int)n_r, dst, st), "correlation kernel launch");
+            continue;
+        }
+        for (uint32_t q0 = 0; q0 < n_r; q0 += spin::kCorrChunk) {
+            const int cnt = (int)((n_r - q0) < (uint32_t)spin::kCorrChunk ? (n_r - q0) : spin::kCorrChunk);
+            HIP_TRY(spin::launch_corr(lat, vertical, r + q0, cnt, dst + 2 * q0, st), "correlation kernel launch");
+        }
+    }
+    return 0;
+}
+
+void finish_measure(const spin_handle *h, const unsigned long long *acc, const uint32_t *r, uint32_t n_r,
+                    spin_meas *out, int64_t *Sx, int64_t *Sy, double *C_hat)
+{
+    const size_t base_x = spin::kEmCounters, base_y = base_x + 2 * (size_t)n_r;
+    const double N = (double)h->L * (double)h->L;
+    out->t = h->t;
+    out->sum_s = (int64_t)acc[0] - 2 * (int64_t)acc[1];
+    out->sum_s2 = (int64_t)acc[0];
+    out->bond = (int64_t)acc[2] - 2 * (int64_t)acc[3];
+    out->e = (-h->J * (double)out->bond + h->Delta * (double)out->sum_s2) / N;
+    out->m = (double)out->sum_s / N;
+    // pairs with both ends non-zero: every pair for Ising (L^2 per axis and r)
+    const int64_t all_pairs = (int64_t)h->L * (int64_t)h->L;
+    for (uint32_t q = 0; q < n_r; ++q) {
+        const int64_t ax = h->model == SPIN_ISING ? all_pairs : (int64_t)acc[base_x + 2 * q];
+        const int64_t ay = h->model == SPIN_ISING ? all_pairs : (int64_t)acc[base_y + 2 * q];
+        Sx[q] = ax - 2 * (int64_t)acc[base_x + 2 * q + 1];
+        Sy[q] = ay - 2 * (int64_t)acc[base_y + 2 * q + 1];
+    }
+    out->xi = xi_from_sums(r, Sx, Sy, n_r, N, (double)out->sum_s2 / N, C_hat);
+}
+
 } // namespace spin_host
 
 using namespace spin_host;
@@ -294,6 +338,8 @@ int spin_sweep_ex(spin_handle *h, uint32_t n, const double *T, uint32_t flags)
         return rc;
     if (flags & ~SPIN_FUSE_MEASURE)
         return fail(-EINVAL, "unknown flags 0x%x", flags);
+    if (h->batch_owned)
+        return fail(-EINVAL, "the handle belongs to a batch: advance it with spin_batch_run");
     if (n > 0 && !T)
         return fail(-EINVAL, "NULL temperature array");
     if (h->t + n > (1ull << 32))
@@ -349,8 +395,8 @@ int spin_measure(spin_handle *h, const uint32_t *r, uint32_t n_r, spin_meas *out
         if (r[q] == 0 || r[q] >= h->L || (q > 0 && r[q] <= r[q - 1]))
             return fail(-EINVAL, "separations must be strictly increasing in (0, L)");
     }
-    const size_t base_x = spin::kEmCounters, base_y = base_x + 2 * (size_t)n_r;
-    if (int rc = ensure_acc(h, base_y + 2 * (size_t)n_r))
+    const size_t entries = measure_counters(n_r);
+    if (int rc = ensure_acc(h, entries))
         return rc;
     if (!h->em_valid) {
         HIP_TRY(spin::launch_fill_u64(h->d_acc, spin::kEmCounters, 0ull, h->stream), "fill kernel launch");
@@ -358,45 +404,17 @@ int spin_measure(spin_handle *h, const uint32_t *r, uint32_t n_r, spin_meas *out
         h->em_valid = true;
     }
     if (n_r > 0) {
-        HIP_TRY(spin::launch_fill_u64(h->d_acc + base_x, 4 * (uint64_t)n_r, 0ull, h->stream), "fill kernel launch");
-        for (int axis = 0; axis < 2; ++axis) {
-            const bool vertical = axis == 1;
-            unsigned long long *dst = h->d_acc + (vertical ? base_y : base_x);
-            const bool fast = vertical ? spin::corr_sparse_y_ok(h->lat, r, (int)n_r)
-                                       : spin::corr_sparse_x_ok(h->lat, r, (int)n_r);
-            if (fast) {
-                HIP_TRY(spin::launch_corr_sparse(h->lat, vertical, (int)n_r, dst, h->stream),
-                        "correlation kernel launch");
-                continue;
-            }
-            for (uint32_t q0 = 0; q0 < n_r; q0 += spin::kCorrChunk) {
-                const int cnt = (int)((n_r - q0) < (uint32_t)spin::kCorrChunk ? (n_r - q0) : spin::kCorrChunk);
-                HIP_TRY(spin::launch_corr(h->lat, vertical, r + q0, cnt, dst + 2 * q0, h->stream),
-                        "correlation kernel launch");
-            }
-        }
+        HIP_TRY(spin::launch_fill_u64(h->d_acc + spin::kEmCounters, 4 * (uint64_t)n_r, 0ull, h->stream),
+                "fill kernel launch");
+        if (int rc = queue_correlations(h->lat, r, n_r, h->d_acc, h->stream))
+            return rc;
     }
-    std::vector<unsigned long long> acc(base_y + 2 * (size_t)n_r);
+    std::vector<unsigned long long> acc(entries);
     HIP_TRY(hipMemcpyAsync(acc.data(), h->d_acc, acc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                            h->stream),
             "hipMemcpyAsync");
     HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-    const double N = (double)h->L * (double)h->L;
-    out->t = h->t;
-    out->sum_s = (int64_t)acc[0] - 2 * (int64_t)acc[1];
-    out->sum_s2 = (int64_t)acc[0];
-    out->bond = (int64_t)acc[2] - 2 * (int64_t)acc[3];
-    out->e = (-h->J * (double)out->bond + h->Delta * (double)out->sum_s2) / N;
-    out->m = (double)out->sum_s / N;
-    // pairs with both ends non-zero: every pair for Ising (L^2 per axis and r)
-    const int64_t all_pairs = (int64_t)h->L * (int64_t)h->L;
-    for (uint32_t q = 0; q < n_r; ++q) {
-        const int64_t ax = h->model == SPIN_ISING ? all_pairs : (int64_t)acc[base_x + 2 * q];
-        const int64_t ay = h->model == SPIN_ISING ? all_pairs : (int64_t)acc[base_y + 2 * q];
-        Sx[q] = ax - 2 * (int64_t)acc[base_x + 2 * q + 1];
-        Sy[q] = ay - 2 * (int64_t)acc[base_y + 2 * q + 1];
-    }
-    out->xi = xi_from_sums(r, Sx, Sy, n_r, N, (double)out->sum_s2 / N, C_hat);
+    finish_measure(h, acc.data(), r, n_r, out, Sx, Sy, C_hat);
     return 0;
 }
 
@@ -505,6 +523,8 @@ int spin_set_t(spin_handle *h, uint64_t t)
         return rc;
     if (t >= (1ull << 32))
         return fail(-EINVAL, "t must be below 2^32");
+    if (h->batch_owned)
+        return fail(-EINVAL, "the handle belongs to a batch, which keeps its sweep index");
     h->t = t;
     return 0;
 }

@@ -10,7 +10,7 @@ the new lattice; admitted lattices stay resident in HBM until their job ends.
 One epoch advances every active job by the same number of sweeps through one
 spin_batch (one launch per half-sweep covers all active lattices, captured as
 a HIP graph), so work of jobs that arrived at different times overlaps on the
-device.  A finished job is measured, its lattice freed, and its slot reused
+device; the batch is kept across epochs until a job joins or leaves.  A finished job is measured, its lattice freed, and its slot reused
 at the next boundary.  Each replica of an epoch continues its own random
 stream (descriptor t0 = sweeps already done), so a job's result does not
 depend on which other jobs shared its epochs.
@@ -23,7 +23,7 @@ from collections import deque
 
 import numpy as np
 
-from . import (BATCH_VARIANT, spin_batch_create, spin_batch_destroy, spin_batch_run, spin_create,
+from . import (BATCH_VARIANT, spin_batch_create, spin_batch_destroy, spin_batch_info, spin_batch_run, spin_create,
                spin_destroy, spin_get_spins, spin_init_random, spin_lattice_bytes, spin_measure,
                spin_replica_desc, spin_set_t)
 from . import workloads
@@ -44,14 +44,26 @@ class Job:
 
 
 class GpuBackend:
-    """Lattices in torch device buffers; one spin_batch per epoch."""
+    """Lattices in torch device buffers, advanced by one spin_batch that lives
+    as long as the set of active jobs does not change.
 
-    def __init__(self, device="cuda", variant=0):
+    The batch is created with a schedule that covers the shortest remaining
+    job, so consecutive epochs of the same jobs replay its captured graph
+    without rebuilding anything; a job joining or leaving (or the schedule
+    running out) makes the next epoch build a new batch whose replicas continue
+    each job's stream (t0 = sweeps done).  The sweep strategy is tuned by the
+    first batch and kept for the later ones."""
+
+    def __init__(self, device="cuda", variant=None):
         import torch
         self.torch = torch
-        self.variant = variant  # sweep strategy of every epoch (no per-epoch tuning)
+        self.variant = variant  # None: tuned by the first batch, then kept
         self.device = torch.device(device)
         self.stream = torch.cuda.Stream(self.device)
+        self.batch = None
+        self.members = None
+        self.steps_left = 0
+        self.batches_built = 0
 
     def free_bytes(self):
         free, _ = self.torch.cuda.mem_get_info(self.device)
@@ -65,18 +77,34 @@ class GpuBackend:
         spin_init_random(h)
         job.state = (buf, h)
 
+    def _release(self):
+        if self.batch is not None:
+            spin_batch_destroy(self.batch)  # waits for the batch's work
+            self.batch = None
+            self.members = None
+            self.steps_left = 0
+
     def epoch(self, jobs, n):
-        temps = sorted({j.T for j in jobs})
-        T = np.array([[tk] * n for tk in temps], dtype=np.float64)
-        descs = [spin_replica_desc(j.model, j.L, j.seed, j.J, j.Delta, j.state[0].data_ptr(), j.bytes,
-                                   temps.index(j.T), j.done) for j in jobs]
-        b = spin_batch_create(descs, T, self.stream.cuda_stream)
-        try:
-            spin_batch_run(b, n, BATCH_VARIANT(self.variant))
-        finally:
-            spin_batch_destroy(b)  # waits for the epoch's work
+        members = tuple(j.id for j in jobs)
+        if self.batch is None or members != self.members or self.steps_left < n:
+            self._release()
+            steps = min(j.sweeps - j.done for j in jobs)
+            temps = sorted({j.T for j in jobs})
+            T = np.array([[tk] * steps for tk in temps], dtype=np.float64)
+            descs = [spin_replica_desc(j.model, j.L, j.seed, j.J, j.Delta, j.state[0].data_ptr(), j.bytes,
+                                       temps.index(j.T), j.done) for j in jobs]
+            self.batch = spin_batch_create(descs, T, self.stream.cuda_stream)
+            self.members = members
+            self.steps_left = steps
+            self.batches_built += 1
+        spin_batch_run(self.batch, n, 0 if self.variant is None else BATCH_VARIANT(self.variant))
+        if self.variant is None:
+            self.variant = spin_batch_info(self.batch)["variant"]
+        self.steps_left -= n
 
     def finish(self, job, r, keep_spins):
+        if self.members is not None and job.id in self.members:
+            self._release()
         buf, h = job.state
         spin_set_t(h, job.done)
         job.result = spin_measure(h, r)
@@ -84,6 +112,9 @@ class GpuBackend:
             job.spins = spin_get_spins(h, job.L)
         spin_destroy(h)
         job.state = None
+
+    def close(self):
+        self._release()
 
 
 class Server:
@@ -170,4 +201,5 @@ class Server:
         return {"jobs": len(self.finished), "wall_s": wall, "jobs_per_s": len(self.finished) / wall,
                 "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
                 "epochs": self.epochs, "flips_per_ns": self.flips / wall / 1e9,
-                "peak_active": self.peak_active, "peak_bytes": self.peak_bytes}
+                "peak_active": self.peak_active, "peak_bytes": self.peak_bytes,
+                "batches_built": getattr(self.backend, "batches_built", None)}

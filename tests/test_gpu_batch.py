@@ -168,3 +168,65 @@ def test_single_model_batches(gpu, model):
         for k in range(len(reps)):
             assert np.array_equal(b.spins(k), want[k]), (v, k)
         b.close()
+
+
+def test_batch_measure_all_fast_kernels_and_reuse(gpu):
+    """The sparse separation prefix takes the fast correlation kernels in the
+    batched measurement too; a second call with fewer separations reuses the
+    counter buffer (it must start from zero again)."""
+    reps = mixed_replicas()
+    T = schedules(8)
+    b = gpu.Batch(reps, T).init_random()
+    b.run(8)
+    for r in (workloads.r_sparse(64), workloads.r_sparse(64)[:5], np.array([], dtype=np.uint32)):
+        got = b.measure_all(r)
+        for k in range(len(reps)):
+            one = b.measure(k, r)
+            assert got[k]["bond"] == one["bond"] and got[k]["sum_s"] == one["sum_s"]
+            assert got[k]["xi"] == one["xi"] and got[k]["e"] == one["e"]
+            assert np.array_equal(got[k]["Sx"], one["Sx"]) and np.array_equal(got[k]["Sy"], one["Sy"])
+    b.close()
+
+
+def test_borrowed_handles_cannot_advance(gpu):
+    """Only spin_batch_run advances a replica: sweeping, cluster-updating or
+    re-timing a borrowed handle is refused, so no sweep index is reused."""
+    reps = mixed_replicas()[:3]
+    T = schedules(4)
+    b = gpu.Batch(reps, T).init_random()
+    b.run(2)
+    h = b.replica(1)
+    for call in (lambda: gpu.spin_sweep(h, [2.0]), lambda: gpu.spin_sw(h, [2.0]),
+                 lambda: gpu.spin_set_t(h, 0)):
+        with pytest.raises(gpu.SpinError) as ei:
+            call()
+        assert ei.value.code == -22
+    assert gpu.spin_get_t(h) == 2
+    b.run(2)
+    s = b.spins(1)
+    assert np.array_equal(s, oracle_run(reps[1], T[reps[1]["schedule"]], 4))
+    b.close()
+
+
+def test_graph_replays_match_direct_runs(gpu):
+    """Runs of equal length replay one captured graph (its launches read the
+    schedule step from the device counter).  Every replay, with eager work
+    and synchronisations in between, must equal direct launches of the same
+    steps, and the end state the oracle's."""
+    reps = mixed_replicas()
+    n, runs = 6, 4
+    T = schedules(n * runs)
+    g = gpu.Batch(reps, T).init_random()
+    d = gpu.Batch(reps, T).init_random()
+    for q in range(runs):
+        g.run(n)
+        d.run(n, gpu.BATCH_DIRECT | gpu.BATCH_VARIANT(g.info()["variant"]))
+        g.measure_all([1, 2])  # eager kernels and a synchronisation between replays
+        d.sync()
+        for k in range(len(reps)):
+            assert np.array_equal(g.spins(k), d.spins(k)), (q, k)
+        assert g.info()["t"] == d.info()["t"] == n * (q + 1)
+    for k, rep in enumerate(reps):
+        assert np.array_equal(g.spins(k), oracle_run(rep, T[rep["schedule"]], n * runs)), k
+    g.close()
+    d.close()
