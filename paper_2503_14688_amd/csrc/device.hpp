@@ -163,6 +163,24 @@ __device__ __forceinline__ uint32_t stream_tag(uint32_t purpose, uint32_t colour
     return (purpose << 16) | (colour << 8) | blk;
 }
 
+// One plane of the lazy test in two three-input operations: the sites of
+// `und` whose bit is 0 against a threshold bit 1 are accepted (und & tb & ~u,
+// truth table 0x40), and those whose bits agree stay undecided
+// (und & ~(tb ^ u), truth table 0x90).
+__device__ __forceinline__ uint32_t newly_accepted(uint32_t und, uint32_t tb, uint32_t u)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x40" : "=v"(r) : "v"(und), "v"(tb), "v"(u));
+    return r;
+}
+
+__device__ __forceinline__ uint32_t still_tied(uint32_t und, uint32_t tb, uint32_t u)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x90" : "=v"(r) : "v"(und), "v"(tb), "v"(u));
+    return r;
+}
+
 // Bit-sliced "u < thr" over the 32 sites of a word, evaluated lazily.
 //
 // Site b's uniform u_b is read plane by plane from the most significant bit
@@ -246,8 +264,58 @@ __device__ __forceinline__ void apply_block_2g(const Block4 &r, uint32_t blk, co
         const uint32_t d = 0u - ((dthr >> shift) & 1u);
         const uint32_t tb = (H & d) ^ m0;
         const uint32_t u = r.v[q];
-        accepted |= undecided & tb & ~u;
-        undecided &= ~(tb ^ u);
+        accepted |= newly_accepted(undecided, tb, u);
+        undecided = still_tied(undecided, tb, u);
+    }
+}
+
+// Threshold bits of the two Ising groups for planes 0..7 (the planes every
+// word draws in place), prepared once per tile: the group-0 bit of plane k
+// as a scalar mask m0[k], and the difference of the two groups' bits as a
+// vector mask d[k] (all ones or zero in every lane).  Kept in vector
+// registers and opaque to the compiler, d[k] lets the plane's threshold
+// word m0 ^ (H & d) be one three-input bitwise operation (the compiler
+// otherwise turns H & d into a select and adds an XOR).
+struct PlaneMasks2 {
+    uint32_t m0[8];
+    uint32_t d[8];
+};
+
+__device__ __forceinline__ PlaneMasks2 plane_masks_2g(const uint32_t (&thr)[2])
+{
+    PlaneMasks2 pm;
+    const uint32_t dthr = thr[0] ^ thr[1];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        pm.m0[k] = 0u - ((thr[0] >> (31 - k)) & 1u);
+        uint32_t d = 0u - ((dthr >> (31 - k)) & 1u);
+        asm volatile("v_mov_b32 %0, %1" : "=v"(d) : "s"(d));
+        pm.d[k] = d;
+    }
+    return pm;
+}
+
+// (h & d) ^ m: gfx950's three-input bitwise operation, truth table 0x6A
+// (operands in order h, d, m); m is wave-uniform.
+__device__ __forceinline__ uint32_t and_xor_s(uint32_t h, uint32_t d, uint32_t m)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x6a" : "=v"(r) : "v"(h), "v"(d), "s"(m));
+    return r;
+}
+
+// apply_block_2g for block 0 or 1 (planes 0..7) with prepared plane masks:
+// three vector operations per plane (and one OR per two planes).
+template <int BLK>
+__device__ __forceinline__ void apply_block_2g_pm(const Block4 &r, const PlaneMasks2 &pm, uint32_t H,
+                                                  uint32_t &undecided, uint32_t &accepted)
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t tb = and_xor_s(H, pm.d[4 * BLK + q], pm.m0[4 * BLK + q]);
+        const uint32_t u = r.v[q];
+        accepted |= newly_accepted(undecided, tb, u);
+        undecided = still_tied(undecided, tb, u);
     }
 }
 
