@@ -223,8 +223,8 @@ __device__ __forceinline__ void apply_block(const Block4 &r, uint32_t blk, const
                 tb |= need[g] & (0u - ((thr[g] >> shift) & 1u));
         }
         const uint32_t ub = r.v[q];
-        accepted |= undecided & tb & ~ub;
-        undecided &= ~(tb ^ ub);
+        accepted |= newly_accepted(undecided, tb, ub);
+        undecided = still_tied(undecided, tb, ub);
     }
 }
 
