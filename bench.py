@@ -415,6 +415,8 @@ def run_equilibrium(args):
         wl["sizes"] = tuple(int(x) for x in args.equilibrium_sizes.split(","))
     if getattr(args, "equilibrium_emcs", None):
         wl["n_emcs"] = args.equilibrium_emcs
+    if getattr(args, "equilibrium_runs", None):
+        wl["runs"] = args.equilibrium_runs
     T, beta0 = wl["T"], 1.0 / wl["T"]
     out = {"workload": wl["name"], "T_sim": T, "Delta": 0.0, "runs_per_L": wl["runs"], "n_therm": wl["n_therm"],
            "n_emcs": wl["n_emcs"], "emcs": "10 Metropolis sweeps + 1 Swendsen-Wang step",
@@ -554,6 +556,8 @@ def main():
                     help="comma-separated L of the equilibrium section (default: the workload's)")
     ap.add_argument("--equilibrium-emcs", type=int, default=None,
                     help="measured EMCS per run of the equilibrium section (default: the workload's)")
+    ap.add_argument("--equilibrium-runs", type=int, default=None,
+                    help="independent runs per L of the equilibrium section (default: the workload's)")
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()

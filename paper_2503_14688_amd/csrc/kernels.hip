@@ -36,6 +36,19 @@ __device__ __forceinline__ uint32_t side_word(uint32_t cur, uint32_t nb, uint32_
     return odd ? ((cur >> 1) | (nb << 31)) : ((cur << 1) | (nb >> 31));
 }
 
+// Row group of a lane's work item g: g / W.  Items of one lattice plane number
+// fewer than 2^32 for every L up to 65536 (and for most larger ones), and then
+// the quotient is taken in 32 bits: far fewer vector instructions than the
+// 64-bit division, which the rest keep.  nitems is wave-uniform, so is the
+// branch.  (Where the row is wave-uniform the division runs on the scalar
+// unit and stays 64-bit.)
+__device__ __forceinline__ uint32_t row_group(uint64_t g, uint32_t W, uint64_t nitems)
+{
+    if (nitems <= 0xFFFFFFFFull)
+        return (uint32_t)g / W;
+    return (uint32_t)(g / W);
+}
+
 // ---------------------------------------------------------------- init --
 
 __global__ __launch_bounds__(kBlock) void k_init_ising(uint32_t *planes, uint32_t L, uint32_t W,
@@ -184,10 +197,14 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
     const bool valid = g < nitems;
     uint32_t rg, w;
     if (UNIFORM) {
-        rg = __builtin_amdgcn_readfirstlane((uint32_t)((tile * kBlock) / W));
+        // W % 64 == 0: the wavefront's 64 items lie in one row group (and L is
+        // a multiple of 4096, so the items fill whole tiles: no lane is past
+        // the end)
+        const uint32_t wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) & ~63u;
+        rg = __builtin_amdgcn_readfirstlane((uint32_t)((tile * kBlock + wave0) / W));
         w = (uint32_t)(g - (uint64_t)rg * W);
     } else {
-        rg = valid ? (uint32_t)(g / W) : 0u;
+        rg = valid ? row_group(g, W, nitems) : 0u;
         w = valid ? (uint32_t)(g - (uint64_t)rg * W) : 0u;
     }
     const uint32_t i0 = rg * R;
@@ -310,7 +327,7 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
 
 // Ising half-sweep of one tile, one word at a time: each thread runs the
 // lazy Metropolis test of its word to completion (no list, no LDS).
-// UNIFORM: W is a multiple of kBlock, so the block's 256 items share one row
+// UNIFORM: W is a multiple of 64, so a wavefront's 64 items share one row
 // group; the row index is then wave-uniform and the counter words that
 // depend only on it and on t start the Philox rounds in scalar registers.
 template <bool MEASURE, int R, bool UNIFORM>
@@ -329,10 +346,14 @@ __device__ __forceinline__ void ising_tile_lazy(const Lattice &lat, uint32_t c, 
     const bool nev3 = gt.never_bits & 1u, nev4 = gt.never_bits & 2u;
     uint32_t rg, w;
     if (UNIFORM) {
-        rg = __builtin_amdgcn_readfirstlane((uint32_t)((tile * kBlock) / W));
+        // W % 64 == 0: the wavefront's 64 items lie in one row group (and L is
+        // a multiple of 4096, so the items fill whole tiles: no lane is past
+        // the end)
+        const uint32_t wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) & ~63u;
+        rg = __builtin_amdgcn_readfirstlane((uint32_t)((tile * kBlock + wave0) / W));
         w = (uint32_t)(g - (uint64_t)rg * W);
     } else {
-        rg = (uint32_t)(g / W);
+        rg = row_group(g, W, nitems);
         w = (uint32_t)(g - (uint64_t)rg * W);
     }
     const uint32_t i0 = rg * R;
@@ -509,7 +530,7 @@ __device__ __forceinline__ void bc_tile(const Lattice &lat, uint32_t c, uint32_t
 #pragma unroll
     for (int q = 0; q < NG; ++q)
         thr[q] = gt.thr[q];
-    const uint32_t rg = (uint32_t)(g / W);
+    const uint32_t rg = row_group(g, W, nitems);
     const uint32_t w = (uint32_t)(g - (uint64_t)rg * W);
     const uint32_t i0 = rg * R;
     const uint32_t wl = (w == 0 ? W : w) - 1u;
@@ -585,7 +606,7 @@ __device__ __forceinline__ void bc_tile_compact(const Lattice &lat, uint32_t c, 
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t g = tile * kBlock + threadIdx.x;
     const bool valid = g < nitems;
-    const uint32_t rg = valid ? (uint32_t)(g / W) : 0u;
+    const uint32_t rg = valid ? row_group(g, W, nitems) : 0u;
     const uint32_t w = valid ? (uint32_t)(g - (uint64_t)rg * W) : 0u;
     const uint32_t i0 = rg * R;
     Q.i0[lane] = i0;
@@ -750,17 +771,17 @@ __global__ __launch_bounds__(kBlock) void k_sweep_ising(Lattice lat, uint32_t c,
         __shared__ WaveList<variant_list_cap(V)> Q[kWaves];
         using QL = WaveList<variant_list_cap(V)>;
         const bool plain = (gt.rng_bits & 3u) == 3u && (gt.never_bits & 3u) == 0u;
-        if (lat.W % kBlock == 0 && plain) {
+        if (lat.W % 64 == 0 && plain) {
             for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
                 ising_tile_compact<MEASURE, R, true, QL, true>(lat, c, t, gt, tile, Q[threadIdx.x >> 6], e);
-        } else if (lat.W % kBlock == 0) {
+        } else if (lat.W % 64 == 0) {
             for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
                 ising_tile_compact<MEASURE, R, true>(lat, c, t, gt, tile, Q[threadIdx.x >> 6], e);
         } else {
             for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
                 ising_tile_compact<MEASURE, R, false>(lat, c, t, gt, tile, Q[threadIdx.x >> 6], e);
         }
-    } else if (lat.W % kBlock == 0) {
+    } else if (lat.W % 64 == 0) {
         for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
             ising_tile_lazy<MEASURE, R, true>(lat, c, t, gt, tile, e);
     } else {
@@ -845,14 +866,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica 
                 if constexpr (variant_compact(V)) {
                     using QL = WaveList<variant_list_cap(V)>;
                     const bool plain = (gt.rng_bits & 3u) == 3u && (gt.never_bits & 3u) == 0u;
-                    if (rep.lat.W % kBlock == 0 && plain)
+                    if (rep.lat.W % 64 == 0 && plain)
                         ising_tile_compact<false, R, true, QL, true>(rep.lat, c, t, gt, local,
                                                                      Q[threadIdx.x >> 6].ising, e);
-                    else if (rep.lat.W % kBlock == 0)
+                    else if (rep.lat.W % 64 == 0)
                         ising_tile_compact<false, R, true>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].ising, e);
                     else
                         ising_tile_compact<false, R, false>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].ising, e);
-                } else if (rep.lat.W % kBlock == 0) {
+                } else if (rep.lat.W % 64 == 0) {
                     ising_tile_lazy<false, R, true>(rep.lat, c, t, gt, local, e);
                 } else {
                     ising_tile_lazy<false, R, false>(rep.lat, c, t, gt, local, e);
