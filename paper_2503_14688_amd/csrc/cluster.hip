@@ -6,15 +6,16 @@
 // Swendsen-Wang step at sweep index t (Swendsen and Wang 1987, on the signs
 // of the non-zero spins, which with s^2 fixed form an Ising model on the
 // bonds between non-zero sites):
-//   1. every site starts as its own cluster (label = linear index i L + j);
-//   2. every bond between two equal non-zero spins is active iff its uniform
+//   1. every bond between two equal non-zero spins is active iff its uniform
 //      u < thr = floor(2^32 (1 - exp(-2J/T))) (all such bonds when the
 //      probability rounds to one); u is word 0 (bond to the right) or word 1
 //      (bond below) of Philox4x32-10 at counter (i, j, t, 3 << 16); the two
-//      ends of an active bond are merged in a lock-free union-find forest
-//      whose roots only ever hook onto smaller roots, so every cluster ends
-//      with its smallest site index as root whatever the order of merges;
-//   3. each non-zero site flips iff its cluster's root n draws word 0 >= 2^31
+//      ends of an active bond are merged in a union-find forest whose roots
+//      only ever hook onto smaller roots (site index i L + j), so every
+//      cluster ends with its smallest site index as root whatever the order
+//      of merges: first inside 16 x 64 tiles in LDS, then across tile edges
+//      in the global forest with lock-free compare-and-swap;
+//   2. each non-zero site flips iff its cluster's root n draws word 0 >= 2^31
 //      from Philox4x32-10 at counter (n, 0, t, 4 << 16).
 // The result depends only on the stream, never on the schedule of the
 // merges, so it is reproducible bit for bit.
@@ -96,29 +97,128 @@ __device__ void unite(uint32_t *P, uint32_t a, uint32_t b)
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_sw_init(uint32_t *P, uint64_t n)
+// Tiled linking: a block first merges the bonds inside its 16 x 64 tile in an
+// LDS forest (the same hooking rule on tile-local indices, whose order is the
+// global order within the tile), then writes every site's parent as the
+// global index of its tile-local root; a second kernel merges the bonds that
+// cross tile edges in the global forest.  Only about one bond in sixteen then
+// touches global atomics.
+constexpr uint32_t kTileRows = 16, kTileCols = 64, kTileSites = kTileRows * kTileCols;
+
+__device__ uint32_t lds_find(uint32_t *lab, uint32_t x)
 {
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (uint64_t)gridDim.x * blockDim.x)
-        P[g] = (uint32_t)g;
+    uint32_t p = __hip_atomic_load(lab + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    while (p != x) {
+        const uint32_t g = __hip_atomic_load(lab + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (g != p)
+            __hip_atomic_store(lab + x, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        x = p;
+        p = g;
+    }
+    return x;
 }
 
-// One thread per site: its bonds to the right and below.
-__global__ __launch_bounds__(kBlock) void k_sw_link(Lattice lat, uint32_t t, uint32_t thr, uint32_t always,
-                                                    uint32_t *P)
+__device__ void lds_unite(uint32_t *lab, uint32_t a, uint32_t b)
+{
+    a = lds_find(lab, a);
+    b = lds_find(lab, b);
+    while (a != b) {
+        if (a < b) {
+            const uint32_t x = a;
+            a = b;
+            b = x;
+        }
+        uint32_t expected = a;
+        if (__hip_atomic_compare_exchange_strong(lab + a, &expected, b, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
+            return;
+        a = lds_find(lab, expected);
+        b = lds_find(lab, b);
+    }
+}
+
+// Whether the bond from (i, j) to its right (dir 0) or lower (dir 1)
+// neighbour is active, given both spins.
+__device__ __forceinline__ bool bond_active(const Lattice &lat, uint32_t i, uint32_t j, uint32_t t, int dir, int s,
+                                            int s_nb, uint32_t thr, uint32_t always)
+{
+    if (s == 0 || s != s_nb)
+        return false;
+    if (always)
+        return true;
+    const Block4 u = philox4x32_10(i, j, t, kPurposeSwBond << 16, lat.key0, lat.key1);
+    return (dir == 0 ? u.v[0] : u.v[1]) < thr;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sw_link_tiles(Lattice lat, uint32_t t, uint32_t thr, uint32_t always,
+                                                          uint32_t *P)
+{
+    __shared__ uint32_t lab[kTileSites];
+    __shared__ int8_t spin[kTileSites];
+    const uint32_t L = lat.L;
+    const uint32_t tiles_x = L / kTileCols;
+    const uint64_t ntiles = (uint64_t)(L / kTileRows) * tiles_x;
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t i0 = (uint32_t)(tile / tiles_x) * kTileRows;
+        const uint32_t j0 = (uint32_t)(tile % tiles_x) * kTileCols;
+        __syncthreads();  // the previous tile is done with lab and spin
+        for (uint32_t q = threadIdx.x; q < kTileSites; q += kBlock) {
+            lab[q] = q;
+            spin[q] = (int8_t)site_spin(lat, i0 + q / kTileCols, j0 + q % kTileCols);
+        }
+        __syncthreads();
+        for (uint32_t q = threadIdx.x; q < kTileSites; q += kBlock) {
+            const uint32_t li = q / kTileCols, lj = q % kTileCols;
+            const int s = spin[q];
+            if (s == 0)
+                continue;
+            const bool in_r = lj + 1 < kTileCols, in_d = li + 1 < kTileRows;
+            const bool need_r = in_r && spin[q + 1] == s, need_d = in_d && spin[q + kTileCols] == s;
+            if (!need_r && !need_d)
+                continue;
+            bool act_r = need_r, act_d = need_d;
+            if (!always) {
+                const Block4 u = philox4x32_10(i0 + li, j0 + lj, t, kPurposeSwBond << 16, lat.key0, lat.key1);
+                act_r = need_r && u.v[0] < thr;
+                act_d = need_d && u.v[1] < thr;
+            }
+            if (act_r)
+                lds_unite(lab, q, q + 1);
+            if (act_d)
+                lds_unite(lab, q, q + kTileCols);
+        }
+        __syncthreads();
+        for (uint32_t q = threadIdx.x; q < kTileSites; q += kBlock) {
+            const uint32_t r = lds_find(lab, q);
+            const uint32_t gi = i0 + q / kTileCols, gj = j0 + q % kTileCols;
+            P[(size_t)gi * L + gj] = (i0 + r / kTileCols) * L + (j0 + r % kTileCols);
+        }
+    }
+}
+
+// The bonds that leave a tile: from its last column to the right and from its
+// last row downwards (periodic), one thread per such site.
+__global__ __launch_bounds__(kBlock) void k_sw_link_edges(Lattice lat, uint32_t t, uint32_t thr, uint32_t always,
+                                                          uint32_t *P)
 {
     const uint32_t L = lat.L;
-    const uint64_t n = (uint64_t)L * L;
+    const uint32_t tiles_x = L / kTileCols;
+    const uint64_t ntiles = (uint64_t)(L / kTileRows) * tiles_x;
+    constexpr uint32_t per_tile = kTileRows + kTileCols;  // last column, then last row
+    const uint64_t n = ntiles * per_tile;
     for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t i = (uint32_t)(g / L), j = (uint32_t)(g - (uint64_t)i * L);
+        const uint64_t tile = g / per_tile;
+        const uint32_t k = (uint32_t)(g - tile * per_tile);
+        const uint32_t i0 = (uint32_t)(tile / tiles_x) * kTileRows;
+        const uint32_t j0 = (uint32_t)(tile % tiles_x) * kTileCols;
+        const int dir = k < kTileRows ? 0 : 1;
+        const uint32_t i = dir == 0 ? i0 + k : i0 + kTileRows - 1;
+        const uint32_t j = dir == 0 ? j0 + kTileCols - 1 : j0 + (k - kTileRows);
+        const uint32_t in = dir == 0 ? i : (i + 1 == L ? 0u : i + 1);
+        const uint32_t jn = dir == 0 ? (j + 1 == L ? 0u : j + 1) : j;
         const int s = site_spin(lat, i, j);
-        if (s == 0)
-            continue;
-        const uint32_t jr = j + 1 == L ? 0u : j + 1, id = i + 1 == L ? 0u : i + 1;
-        const Block4 u = philox4x32_10(i, j, t, kPurposeSwBond << 16, lat.key0, lat.key1);
-        if (site_spin(lat, i, jr) == s && (always || u.v[0] < thr))
-            unite(P, (uint32_t)g, i * L + jr);
-        if (site_spin(lat, id, j) == s && (always || u.v[1] < thr))
-            unite(P, (uint32_t)g, id * L + j);
+        if (bond_active(lat, i, j, t, dir, s, site_spin(lat, in, jn), thr, always))
+            unite(P, i * L + j, in * L + jn);
     }
 }
 
@@ -202,9 +302,11 @@ __global__ __launch_bounds__(kBlock) void k_col_sums(Lattice lat, uint32_t rows_
 hipError_t launch_sw_step(const Lattice &lat, uint32_t t, uint32_t thr, bool always, uint32_t *labels,
                           hipStream_t st)
 {
-    const uint64_t n = (uint64_t)lat.L * lat.L;
-    hipLaunchKernelGGL(k_sw_init, dim3(grid_for(n)), dim3(kBlock), 0, st, labels, n);
-    hipLaunchKernelGGL(k_sw_link, dim3(grid_for(n)), dim3(kBlock), 0, st, lat, t, thr, always ? 1u : 0u, labels);
+    const uint64_t ntiles = (uint64_t)(lat.L / kTileRows) * (lat.L / kTileCols);
+    const unsigned gt = (unsigned)(ntiles < 65536 ? ntiles : 65536);
+    hipLaunchKernelGGL(k_sw_link_tiles, dim3(gt), dim3(kBlock), 0, st, lat, t, thr, always ? 1u : 0u, labels);
+    hipLaunchKernelGGL(k_sw_link_edges, dim3(grid_for(ntiles * (kTileRows + kTileCols))), dim3(kBlock), 0, st, lat,
+                       t, thr, always ? 1u : 0u, labels);
     hipLaunchKernelGGL(k_sw_flip, dim3(grid_for(2ull * lat.L * lat.W)), dim3(kBlock), 0, st, lat, t,
                        (const uint32_t *)labels);
     return hipGetLastError();
