@@ -197,6 +197,8 @@ class Server:
             elif k < len(pending):
                 time.sleep(max(0.0, pending[k].arrival - now()))
         wall = now()
+        if hasattr(self.backend, "close"):
+            self.backend.close()  # the last batch's device tables
         lat = np.array([j.finished_at - j.arrival for j in self.finished])
         return {"jobs": len(self.finished), "wall_s": wall, "jobs_per_s": len(self.finished) / wall,
                 "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),

@@ -230,3 +230,22 @@ def test_graph_replays_match_direct_runs(gpu):
         assert np.array_equal(g.spins(k), oracle_run(rep, T[rep["schedule"]], n * runs)), k
     g.close()
     d.close()
+
+
+def test_row_uniform_replicas_match_oracle(gpu):
+    """Ising replicas whose rows are a multiple of 64 words (L = 4096) take
+    the row-uniform Philox path of the batched kernel, next to Ising replicas
+    whose rows are not (L = 192) and Blume-Capel replicas of both sizes in the
+    same launch: every strategy gives the oracle's lattices."""
+    reps = [dict(model=m, L=L, seed=workloads.seed_for(900 + 10 * m + k), J=1.0, Delta=0.0, schedule=m)
+            for m in (0, 1) for k, L in enumerate((4096, 192))]
+    n = 6
+    T = np.stack([np.full(n, workloads.TC_ISING), np.full(n, workloads.TC_BC)])
+    want = [oracle_run(rep, T[rep["schedule"]], n) for rep in reps]
+    for v in range(5):
+        b = gpu.Batch(reps, T).init_random()
+        b.run(n, gpu.BATCH_VARIANT(v))
+        b.sync()
+        for k in range(len(reps)):
+            assert np.array_equal(b.spins(k), want[k]), (v, k)
+        b.close()
