@@ -267,10 +267,15 @@ typedef struct spin_replica_desc {
 } spin_replica_desc;
 
 /* spin_batch_run flags: SPIN_BATCH_DIRECT launches directly instead of
- * capturing a graph; SPIN_BATCH_VARIANT(v) forces sweep strategy v (see
- * spin_set_variant) instead of the tuned one. */
+ * capturing a graph; SPIN_BATCH_VARIANT(v) forces batched strategy v,
+ * 0 <= v < SPIN_BATCH_VARIANTS, instead of the tuned one.  A batched strategy
+ * is a pair of sweep strategies (see spin_set_variant), one for the Ising and
+ * one for the Blume-Capel replicas: v = 0..4 runs strategy v for both; 5, 6
+ * and 7 run (Ising, Blume-Capel) = (2, 0), (2, 3) and (1, 3).  Every strategy
+ * gives the same lattices. */
 #define SPIN_BATCH_DIRECT 1u
 #define SPIN_BATCH_VARIANT(v) ((uint32_t)((v) + 1) << 4)
+#define SPIN_BATCH_VARIANTS 8
 
 /* Create a batch of n replicas.  T holds n_sched schedules of
  * n_steps temperatures each: T[s * n_steps + k] is the bath temperature of
@@ -312,7 +317,7 @@ int spin_batch_replica(spin_batch *b, uint32_t k, spin_handle **out);
 int spin_batch_measure(spin_batch *b, const uint32_t *r, uint32_t n_r, spin_meas *out, int64_t *Sx,
                        int64_t *Sy);
 
-/* Replica count, sweeps this batch has run, sweep strategy in use (-1 before
+/* Replica count, sweeps this batch has run, batched strategy in use (-1 before
  * the first run) and tiles per half-sweep; any output may be NULL. */
 int spin_batch_info(const spin_batch *b, uint32_t *n_replicas, uint64_t *t, int *variant, uint64_t *tiles);
 

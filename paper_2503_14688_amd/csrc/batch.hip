@@ -19,6 +19,10 @@
 
 using namespace spin_host;
 
+// Tile layouts: rows per thread of the Ising tiles (4 or 8) x of the
+// Blume-Capel tiles.
+constexpr int kLayouts = 4;
+
 struct spin_batch {
     std::vector<spin_handle *> reps;
     std::vector<uint32_t> table_of;     // replica -> threshold table id
@@ -27,11 +31,12 @@ struct spin_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     uint64_t t = 0;                      // sweeps done (schedule step)
-    int variant = -1;                    // sweep strategy in use (-1: tune at first run)
+    int variant = -1;                    // batched strategy in use (-1: tune at first run)
     int models = 0;                      // spin::BatchModels bits of the replicas
-    spin::BatchReplica *d_reps[2] = {nullptr, nullptr};  // per tile shape
-    uint32_t *d_tile_rep[2] = {nullptr, nullptr};
-    uint64_t ntiles[2] = {0, 0};
+    // per tile layout (rows per thread of the Ising and of the Blume-Capel tiles)
+    spin::BatchReplica *d_reps[kLayouts] = {};
+    uint32_t *d_tile_rep[kLayouts] = {};
+    uint64_t ntiles[kLayouts] = {};
     GroupTable *d_tables = nullptr;
     unsigned long long *d_meas = nullptr;  // measurement counters of every replica
     size_t meas_cap = 0;                   // entries
@@ -44,8 +49,13 @@ struct spin_batch {
 
 namespace {
 
-int shape_index(int rows) { return rows == 4 ? 0 : 1; }
-int shape_of(int variant) { return shape_index(spin::variant_rows(variant)); }
+// Tile layout of a batched strategy: bit 0 set when its Ising tiles walk 8
+// rows per thread (else 4), bit 1 the same for its Blume-Capel tiles.
+int layout_of(int bv)
+{
+    return (spin::variant_rows(spin::batch_ising_variant(bv)) == 8 ? 1 : 0) |
+           (spin::variant_rows(spin::batch_bc_variant(bv)) == 8 ? 2 : 0);
+}
 
 void release(spin_batch *b)
 {
@@ -57,7 +67,7 @@ void release(spin_batch *b)
         (void)hipGraphExecDestroy(b->exec);
     if (b->graph)
         (void)hipGraphDestroy(b->graph);
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < kLayouts; ++k) {
         if (b->d_reps[k])
             (void)hipFree(b->d_reps[k]);
         if (b->d_tile_rep[k])
@@ -76,15 +86,17 @@ void release(spin_batch *b)
     delete b;
 }
 
-// Tile list for one tile shape: replicas with more tiles first (they bound
-// the half-sweep's duration), each replica's tiles contiguous.
-int build_tiles(spin_batch *b, int rows)
+// Tile list for one tile layout k (see layout_of): replicas with more tiles
+// first (they bound the half-sweep's duration), each replica's tiles
+// contiguous.
+int build_tiles(spin_batch *b, int k)
 {
-    const int k = shape_index(rows);
     const size_t n = b->reps.size();
     std::vector<uint64_t> tiles(n);
-    for (size_t r = 0; r < n; ++r)
-        tiles[r] = spin::sweep_tiles(b->reps[r]->lat, rows);
+    for (size_t r = 0; r < n; ++r) {
+        const bool ising = b->reps[r]->lat.model == spin::kIsing;
+        tiles[r] = spin::sweep_tiles(b->reps[r]->lat, (k & (ising ? 1 : 2)) ? 8 : 4);
+    }
     std::vector<uint32_t> order(n);
     for (size_t r = 0; r < n; ++r)
         order[r] = (uint32_t)r;
@@ -117,7 +129,7 @@ int build_tiles(spin_batch *b, int rows)
 // repeated at the current step (tuning).
 int launch_sweeps(spin_batch *b, int variant, uint32_t n, bool advance, hipStream_t st)
 {
-    const int k = shape_of(variant);
+    const int k = layout_of(variant);
     for (uint32_t q = 0; q < n; ++q) {
         for (uint32_t c = 0; c < 2; ++c)
             HIP_TRY(spin::launch_batch_half_sweep(variant, b->models, b->d_reps[k], b->d_tile_rep[k], b->ntiles[k],
@@ -129,11 +141,13 @@ int launch_sweeps(spin_batch *b, int variant, uint32_t n, bool advance, hipStrea
     return 0;
 }
 
-// Choose the sweep strategy on scratch copies of every lattice.  The cost of
-// a sweep grows as a lattice relaxes from its T = infinity start, so the
+// Choose the batched strategy on scratch copies of every lattice.  The cost
+// of a sweep grows as a lattice relaxes from its T = infinity start, so the
 // copies are first warmed up with eight sweeps at the current schedule step;
 // then every strategy is timed (HIP events, two sweeps) in three interleaved
 // rounds on the same evolving copies, and the best time of each counts.
+// Strategies that run the batch's models exactly as an earlier one does (in
+// a one-model batch, the other model's half of the pair) are skipped.
 int autotune(spin_batch *b)
 {
     auto padded = [](size_t bytes) { return (bytes + 255) / 256 * 256; };
@@ -146,10 +160,22 @@ int autotune(spin_batch *b)
         b->variant = 0;  // no room to tune: keep the default strategy
         return 0;
     }
-    spin::BatchReplica *keep[2] = {b->d_reps[0], b->d_reps[1]};
-    spin::BatchReplica *tmp[2] = {nullptr, nullptr};
+    spin::BatchReplica *keep[kLayouts], *tmp[kLayouts] = {};
+    for (int k = 0; k < kLayouts; ++k)
+        keep[k] = b->d_reps[k];
+    bool timed[spin::kBatchVariants] = {};
+    for (int v = 0; v < spin::kBatchVariants; ++v) {
+        timed[v] = true;
+        for (int u = 0; u < v && timed[v]; ++u) {
+            const bool same_i = !(b->models & spin::kBatchIsing) ||
+                                spin::batch_ising_variant(u) == spin::batch_ising_variant(v);
+            const bool same_b = !(b->models & spin::kBatchBc) || spin::batch_bc_variant(u) == spin::batch_bc_variant(v);
+            if (same_i && same_b)
+                timed[v] = false;
+        }
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    float best_ms[spin::kVariants] = {};
+    float best_ms[spin::kBatchVariants] = {};
     int rc = 0;
     hipError_t e = hipSuccess;
     do {
@@ -163,7 +189,7 @@ int autotune(spin_batch *b)
         // descriptor copies pointing at the scratch lattices, per tile shape
         const size_t n = b->reps.size();
         std::vector<spin::BatchReplica> host(n);
-        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        for (int k = 0; k < kLayouts && e == hipSuccess; ++k) {
             if ((e = hipMemcpy(host.data(), keep[k], n * sizeof(spin::BatchReplica), hipMemcpyDeviceToHost)) !=
                 hipSuccess)
                 break;
@@ -180,14 +206,16 @@ int autotune(spin_batch *b)
             e = hipEventCreate(&e1);
         if (e != hipSuccess)
             break;
-        b->d_reps[0] = tmp[0];
-        b->d_reps[1] = tmp[1];
+        for (int k = 0; k < kLayouts; ++k)
+            b->d_reps[k] = tmp[k];
         // the current schedule step is the only one known to exist: every
         // tuning sweep uses it
         for (int w = 0; w < 8 && rc == 0; ++w)
             rc = launch_sweeps(b, 0, 1, false, b->stream);
         for (int round = 0; round < 3 && rc == 0 && e == hipSuccess; ++round) {
-            for (int v = 0; v < spin::kVariants && rc == 0 && e == hipSuccess; ++v) {
+            for (int v = 0; v < spin::kBatchVariants && rc == 0 && e == hipSuccess; ++v) {
+                if (!timed[v])
+                    continue;
                 if ((e = hipEventRecord(e0, b->stream)) != hipSuccess)
                     break;
                 rc = launch_sweeps(b, v, 2, false, b->stream);
@@ -201,12 +229,12 @@ int autotune(spin_batch *b)
             }
         }
     } while (false);
-    b->d_reps[0] = keep[0];
-    b->d_reps[1] = keep[1];
+    for (int k = 0; k < kLayouts; ++k)
+        b->d_reps[k] = keep[k];
     if (rc == 0 && e != hipSuccess)
         rc = hip_fail(e, "batch strategy tuning");
     (void)hipStreamSynchronize(b->stream);
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < kLayouts; ++k)
         if (tmp[k])
             (void)hipFree(tmp[k]);
     if (e0)
@@ -217,8 +245,8 @@ int autotune(spin_batch *b)
     if (rc)
         return rc;
     int best = 0;
-    for (int v = 1; v < spin::kVariants; ++v)
-        if (best_ms[v] < best_ms[best])
+    for (int v = 1; v < spin::kBatchVariants; ++v)
+        if (timed[v] && best_ms[v] < best_ms[best])
             best = v;
     b->variant = best;
     return 0;
@@ -319,8 +347,8 @@ int spin_batch_create(uint32_t n, const spin_replica_desc *descs, uint32_t n_sch
         release(b);
         return hip_fail(e, "step counter");
     }
-    for (int rows : {4, 8}) {
-        int rc = build_tiles(b, rows);
+    for (int k = 0; k < kLayouts; ++k) {
+        int rc = build_tiles(b, k);
         if (rc) {
             std::string msg = spin_last_error();
             release(b);
@@ -346,7 +374,7 @@ int spin_batch_run(spin_batch *b, uint32_t n, uint32_t flags)
     if (!b)
         return fail(-EINVAL, "NULL batch");
     const uint32_t forced = (flags >> 4) & 0xFu;
-    if ((flags & ~(SPIN_BATCH_DIRECT | 0xF0u)) || forced > (uint32_t)spin::kVariants)
+    if ((flags & ~(SPIN_BATCH_DIRECT | 0xF0u)) || forced > (uint32_t)spin::kBatchVariants)
         return fail(-EINVAL, "unknown flags 0x%x", flags);
     if (b->t + n > b->n_steps)
         return fail(-EINVAL, "schedule has %u steps, %llu done, %u asked", b->n_steps, (unsigned long long)b->t, n);
@@ -478,7 +506,7 @@ int spin_batch_info(const spin_batch *b, uint32_t *n_replicas, uint64_t *t, int 
     if (variant)
         *variant = b->variant;
     if (tiles)
-        *tiles = b->variant >= 0 ? b->ntiles[shape_of(b->variant)] : 0;
+        *tiles = b->variant >= 0 ? b->ntiles[layout_of(b->variant)] : 0;
     return 0;
 }
 

@@ -754,11 +754,18 @@ struct IsingList {
 };
 
 // LDS of the batched kernel, per wavefront: only the lists of the models the
-// batch holds (an Ising-only batch keeps the Ising kernel's smaller LDS, so
-// as many blocks fit on a CU as in the single-lattice launch).
-template <int V, int MODELS>
-using BatchList = std::conditional_t<MODELS == kBatchIsing, IsingList<V>,
-                                     std::conditional_t<MODELS == kBatchBc, BcListUnion<V>, AnyList<V>>>;
+// batch holds and of the strategies it runs them with (an Ising-only batch
+// keeps the Ising kernel's smaller LDS, so as many blocks fit on a CU as in
+// the single-lattice launch; a per-word strategy needs no list).
+template <int BV, int MODELS>
+union BatchList {
+    static constexpr int VI = batch_ising_variant(BV), VB = batch_bc_variant(BV);
+    static constexpr bool kIsingList = (MODELS & kBatchIsing) != 0 && variant_compact(VI);
+    static constexpr bool kBcList = (MODELS & kBatchBc) != 0 && variant_compact(VB);
+    std::conditional_t<kIsingList, WaveList<variant_list_cap(VI)>, char> ising;
+    std::conditional_t<kBcList, BcList<kBcGroupsDelta0, bc_list_cap(VB), variant_rows(VB)>, char> d0;
+    std::conditional_t<kBcList, BcList<kBcGroups, bc_list_cap(VB), variant_rows(VB)>, char> gen;
+};
 
 template <bool MEASURE, int V>
 __global__ __launch_bounds__(kBlock) void k_sweep_ising(Lattice lat, uint32_t c, uint32_t t, GroupTable gt,
@@ -837,19 +844,20 @@ __device__ __forceinline__ T wave_uniform_copy(const T *p)
     return out;
 }
 
-template <int V, int MODELS>
+template <int BV, int MODELS>
 __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica *__restrict__ reps,
                                                              const uint32_t *__restrict__ tile_rep, uint64_t ntiles,
                                                              const GroupTable *__restrict__ tables, uint32_t stride,
                                                              const uint32_t *__restrict__ step_base, uint32_t step_off,
                                                              uint32_t c)
 {
-    constexpr int R = variant_rows(V);
+    constexpr int VI = batch_ising_variant(BV), VB = batch_bc_variant(BV);
+    constexpr int RI = variant_rows(VI), RB = variant_rows(VB);
     // schedule step: the batch's device step counter (advanced at the end of
     // every run) plus this launch's offset in the run, so that a captured
     // run can be replayed for the next steps unchanged
     const uint32_t step = __builtin_amdgcn_readfirstlane(*step_base) + step_off;
-    __shared__ std::conditional_t<variant_compact(V), BatchList<V, MODELS>, int> Q[kWaves];
+    __shared__ BatchList<BV, MODELS> Q[kWaves];
     unsigned long long e[kEmCounters] = {0, 0, 0, 0};
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         // The tile, hence its replica, is the same for the whole block: keep
@@ -863,32 +871,32 @@ __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica 
         const uint32_t t = rep.t0 + step;
         if (rep.lat.model == kIsing) {
             if constexpr ((MODELS & kBatchIsing) != 0) {
-                if constexpr (variant_compact(V)) {
-                    using QL = WaveList<variant_list_cap(V)>;
+                if constexpr (variant_compact(VI)) {
+                    using QL = WaveList<variant_list_cap(VI)>;
                     const bool plain = (gt.rng_bits & 3u) == 3u && (gt.never_bits & 3u) == 0u;
                     if (rep.lat.W % 64 == 0 && plain)
-                        ising_tile_compact<false, R, true, QL, true>(rep.lat, c, t, gt, local,
-                                                                     Q[threadIdx.x >> 6].ising, e);
+                        ising_tile_compact<false, RI, true, QL, true>(rep.lat, c, t, gt, local,
+                                                                      Q[threadIdx.x >> 6].ising, e);
                     else if (rep.lat.W % 64 == 0)
-                        ising_tile_compact<false, R, true>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].ising, e);
+                        ising_tile_compact<false, RI, true>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].ising, e);
                     else
-                        ising_tile_compact<false, R, false>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].ising, e);
+                        ising_tile_compact<false, RI, false>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].ising, e);
                 } else if (rep.lat.W % 64 == 0) {
-                    ising_tile_lazy<false, R, true>(rep.lat, c, t, gt, local, e);
+                    ising_tile_lazy<false, RI, true>(rep.lat, c, t, gt, local, e);
                 } else {
-                    ising_tile_lazy<false, R, false>(rep.lat, c, t, gt, local, e);
+                    ising_tile_lazy<false, RI, false>(rep.lat, c, t, gt, local, e);
                 }
             }
         } else if constexpr ((MODELS & kBatchBc) != 0) {
-            if constexpr (variant_compact(V)) {
+            if constexpr (variant_compact(VB)) {
                 if (rep.lat.bc_groups == kBcGroupsDelta0)
-                    bc_tile_compact<false, R, kBcGroupsDelta0>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].d0, e);
+                    bc_tile_compact<false, RB, kBcGroupsDelta0>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].d0, e);
                 else
-                    bc_tile_compact<false, R, kBcGroups>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].gen, e);
+                    bc_tile_compact<false, RB, kBcGroups>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].gen, e);
             } else if (rep.lat.bc_groups == kBcGroupsDelta0) {
-                bc_tile<false, R, kBcGroupsDelta0>(rep.lat, c, t, gt, local, e);
+                bc_tile<false, RB, kBcGroupsDelta0>(rep.lat, c, t, gt, local, e);
             } else {
-                bc_tile<false, R, kBcGroups>(rep.lat, c, t, gt, local, e);
+                bc_tile<false, RB, kBcGroups>(rep.lat, c, t, gt, local, e);
             }
         }
     }
@@ -1163,6 +1171,9 @@ hipError_t launch_batch_half_sweep(int variant, int models, const BatchReplica *
     case 2: return launch_batch_v<2>(models, reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
     case 3: return launch_batch_v<3>(models, reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
     case 4: return launch_batch_v<4>(models, reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
+    case 5: return launch_batch_v<5>(models, reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
+    case 6: return launch_batch_v<6>(models, reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
+    case 7: return launch_batch_v<7>(models, reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -50,6 +50,15 @@ __host__ __device__ constexpr int variant_rows(int v) { return (v == 1 || v == 3
 __host__ __device__ constexpr bool variant_compact(int v) { return v == 1 || v == 2 || v == 4; }
 __host__ __device__ constexpr int variant_list_cap(int v) { return v == 4 ? 16 : 128; }
 
+// Strategies of the batched kernel: one sweep strategy for the Ising tiles
+// and one for the Blume-Capel tiles of the same launch.  0..4 use strategy v
+// for both models; 5..7 pair a compacting Ising tile with a per-word
+// Blume-Capel one (the best single-lattice pairing): 5 = (2, 0), 6 = (2, 3),
+// 7 = (1, 3) as (Ising strategy, Blume-Capel strategy).
+constexpr int kBatchVariants = 8;
+__host__ __device__ constexpr int batch_ising_variant(int bv) { return bv < 5 ? bv : (bv == 7 ? 1 : 2); }
+__host__ __device__ constexpr int batch_bc_variant(int bv) { return bv < 5 ? bv : (bv == 5 ? 0 : 3); }
+
 // Counters of the energy/magnetisation reduction (both colours):
 //   acc[0] = #(s != 0)  acc[1] = #(s < 0)
 //   acc[2] = #bonds with both ends non-zero, acc[3] = #such bonds anti-aligned

@@ -28,6 +28,15 @@ def test_header_declares_the_bound_functions():
     assert sorted(spin.EXPORTS) == names
 
 
+def test_batch_flags_match_header():
+    text = open(os.path.join(ROOT, "include", "spin.h")).read()
+    assert int(re.search(r"#define SPIN_BATCH_VARIANTS (\d+)", text).group(1)) == spin.BATCH_VARIANTS
+    assert spin.BATCH_VARIANT(0) == 1 << 4 and spin.BATCH_VARIANT(spin.BATCH_VARIANTS - 1) == spin.BATCH_VARIANTS << 4
+    for bad in (-1, spin.BATCH_VARIANTS):
+        with pytest.raises(ValueError):
+            spin.BATCH_VARIANT(bad)
+
+
 def test_library_exports_every_declared_symbol():
     lib = spin.load_library()
     for name in declared_functions():

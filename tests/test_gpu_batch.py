@@ -51,7 +51,7 @@ def test_batch_matches_oracle(gpu, flags):
     b.run(n, flags)
     b.sync()
     info = b.info()
-    assert info["t"] == n and info["variant"] in range(5) and info["replicas"] == len(reps)
+    assert info["t"] == n and info["variant"] in range(gpu.BATCH_VARIANTS) and info["replicas"] == len(reps)
     for k, rep in enumerate(reps):
         assert np.array_equal(b.spins(k), oracle_run(rep, T[rep["schedule"]], n)), (k, rep)
     b.close()
@@ -117,7 +117,7 @@ def test_many_tiles_per_block_mixed_models(gpu):
         solo.sweep(T[rep["schedule"]])
         want.append(solo.spins())
         solo.close()
-    for v in (1, 2, 4):
+    for v in (1, 2, 4, 5, 6, 7):
         b = gpu.Batch(reps, T).init_random()
         b.run(n, gpu.BATCH_VARIANT(v))
         b.sync()
@@ -161,7 +161,7 @@ def test_single_model_batches(gpu, model):
     n = 12
     T = schedules(n)
     want = [oracle_run(rep, T[rep["schedule"]], n) for rep in reps]
-    for v in range(5):
+    for v in range(gpu.BATCH_VARIANTS):
         b = gpu.Batch(reps, T).init_random()
         b.run(n, gpu.BATCH_VARIANT(v))
         b.sync()
@@ -242,7 +242,7 @@ def test_row_uniform_replicas_match_oracle(gpu):
     n = 6
     T = np.stack([np.full(n, workloads.TC_ISING), np.full(n, workloads.TC_BC)])
     want = [oracle_run(rep, T[rep["schedule"]], n) for rep in reps]
-    for v in range(5):
+    for v in range(gpu.BATCH_VARIANTS):
         b = gpu.Batch(reps, T).init_random()
         b.run(n, gpu.BATCH_VARIANT(v))
         b.sync()
