@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0
 # in profiles/k_sweep_traffic_ising_L1048576_bc_L262144.txt.  Valid only for
 # the sweep sources it was taken with (their SHA-256 below, first 16 hex
 # digits); any change to those sources makes the bench report null.
-SWEEP_SOURCES = ["paper_2503_14688_amd/csrc/kernels.hip", "paper_2503_14688_amd/csrc/device.hpp",
-                 "paper_2503_14688_amd/csrc/kernels.hpp"]
+SWEEP_SOURCES = ["paper_2503_14688_amd/csrc/kernels.hip", "paper_2503_14688_amd/csrc/sweep_tiles.hpp",
+                 "paper_2503_14688_amd/csrc/device.hpp", "paper_2503_14688_amd/csrc/kernels.hpp"]
 MEASURED_TRAFFIC = {
     # (workload, sweep strategy): bytes per launch
     ("ising_L1048576_tc", 2): 221.55e9,

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libspin.so")
-SOURCES = ["kernels.hip", "corr.hip", "spin.hip", "batch.hip", "measure_noalloc.hip", "cluster.hip",
+SOURCES = ["kernels.hip", "batch_kernels.hip", "corr.hip", "spin.hip", "batch.hip", "measure_noalloc.hip", "cluster.hip",
            "equilibrium.hip"]
 ARCH = "gfx950"
 

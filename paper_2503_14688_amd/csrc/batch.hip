@@ -6,6 +6,7 @@
 // and replayed for every later run of n sweeps; the sweep strategy (rows per thread,
 // per-word or compacting lazy test) is chosen by timing every strategy on
 // scratch copies of the lattices.
+#include "batch_kernels.hpp"
 #include "host.hpp"
 
 #include <algorithm>

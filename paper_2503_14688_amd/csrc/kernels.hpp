@@ -1,5 +1,7 @@
-// Internal launch interface between the C ABI (spin.hip) and the gfx950
-// kernels (kernels.hip).  Not part of the public ABI.
+// Internal launch interface between the C ABI (spin.hip and the other host
+// sources) and the gfx950 kernels (kernels.hip, corr.hip, cluster.hip; the
+// batched kernel's interface is batch_kernels.hpp).  Not part of the public
+// ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -50,44 +52,16 @@ __host__ __device__ constexpr int variant_rows(int v) { return (v == 1 || v == 3
 __host__ __device__ constexpr bool variant_compact(int v) { return v == 1 || v == 2 || v == 4; }
 __host__ __device__ constexpr int variant_list_cap(int v) { return v == 4 ? 16 : 128; }
 
-// Strategies of the batched kernel: one sweep strategy for the Ising tiles
-// and one for the Blume-Capel tiles of the same launch.  0..4 use strategy v
-// for both models; 5..7 pair a compacting Ising tile with a per-word
-// Blume-Capel one (the best single-lattice pairing): 5 = (2, 0), 6 = (2, 3),
-// 7 = (1, 3) as (Ising strategy, Blume-Capel strategy).
-constexpr int kBatchVariants = 8;
-__host__ __device__ constexpr int batch_ising_variant(int bv) { return bv < 5 ? bv : (bv == 7 ? 1 : 2); }
-__host__ __device__ constexpr int batch_bc_variant(int bv) { return bv < 5 ? bv : (bv == 5 ? 0 : 3); }
-
 // Counters of the energy/magnetisation reduction (both colours):
 //   acc[0] = #(s != 0)  acc[1] = #(s < 0)
 //   acc[2] = #bonds with both ends non-zero, acc[3] = #such bonds anti-aligned
 // so sum s = acc0 - 2 acc1, sum s^2 = acc0, bond sum = acc2 - 2 acc3.
 constexpr int kEmCounters = 4;
 
-// One replica of a batch: its lattice, its schedule and its first tile in
-// the batch's flat tile list.
-struct BatchReplica {
-    Lattice lat;
-    uint32_t sched;
-    uint32_t t0;    // sweep index of schedule step 0
-    uint64_t tile0;
-};
-
 hipError_t launch_init(const Lattice &lat, hipStream_t st);
 // Sweep work units (tiles of 256 word columns x rows) of one lattice for a
-// rows-per-thread choice (4 or 8), and the batched half-sweep over a flat
-// tile list of many lattices.
+// rows-per-thread choice (4 or 8).
 uint64_t sweep_tiles(const Lattice &lat, int rows);
-// Models present in a batch (bit 0 Ising, bit 1 Blume-Capel): the batched
-// kernel is specialised on it.
-enum BatchModels : int { kBatchIsing = 1, kBatchBc = 2, kBatchMixed = 3 };
-// The schedule step of a launch is *step_base + step (step_base: the batch's
-// device step counter, which launch_advance_step moves on by n after a run).
-hipError_t launch_batch_half_sweep(int variant, int models, const BatchReplica *reps, const uint32_t *tile_rep,
-                                   uint64_t ntiles, const GroupTable *tables, uint32_t stride,
-                                   const uint32_t *step_base, uint32_t step, uint32_t colour, hipStream_t st);
-hipError_t launch_advance_step(uint32_t *step, uint32_t n, hipStream_t st);
 hipError_t launch_half_sweep(const Lattice &lat, uint32_t colour, uint32_t t, const GroupTable &gt,
                              unsigned long long *em_acc, hipStream_t st);
 hipError_t launch_measure_em(const Lattice &lat, unsigned long long *em_acc, hipStream_t st);
