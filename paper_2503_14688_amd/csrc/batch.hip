@@ -306,6 +306,8 @@ int spin_batch_create(uint32_t n, const spin_replica_desc *descs, uint32_t n_sch
         h->t = d.t0;
         h->batch_owned = true;
         b->models |= d.model == SPIN_ISING ? spin::kBatchIsing : spin::kBatchBc;
+        if (d.model != SPIN_ISING && h->lat.bc_groups != spin::kBcGroupsDelta0)
+            b->models |= spin::kBatchBcGeneral;
         b->reps.push_back(h);
         b->t0.push_back(d.t0);
         auto key = std::make_tuple(d.model, d.J, d.Delta, d.schedule);

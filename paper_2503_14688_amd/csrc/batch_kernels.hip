@@ -18,9 +18,10 @@ union BatchList {
     static constexpr int VI = batch_ising_variant(BV), VB = batch_bc_variant(BV);
     static constexpr bool kIsingList = (MODELS & kBatchIsing) != 0 && variant_compact(VI);
     static constexpr bool kBcList = (MODELS & kBatchBc) != 0 && variant_compact(VB);
+    static constexpr bool kGenList = (MODELS & kBatchBcGeneral) != 0 && variant_compact(VB);
     std::conditional_t<kIsingList, WaveList<variant_list_cap(VI)>, char> ising;
     std::conditional_t<kBcList, BcList<kBcGroupsDelta0, bc_list_cap(VB), variant_rows(VB)>, char> d0;
-    std::conditional_t<kBcList, BcList<kBcGroups, bc_list_cap(VB), variant_rows(VB)>, char> gen;
+    std::conditional_t<kGenList, BcList<kBcGroups, bc_list_cap(VB), variant_rows(VB)>, char> gen;
 };
 
 // Batched half-sweep: one launch advances colour c of every replica.  The
@@ -88,21 +89,22 @@ __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica 
                 }
             }
         } else if constexpr ((MODELS & kBatchBc) != 0) {
-            const bool delta0 = rep.lat.bc_groups == kBcGroupsDelta0;
+            const bool delta0 = (MODELS & kBatchBcGeneral) == 0 || rep.lat.bc_groups == kBcGroupsDelta0;
             if constexpr (variant_compact(VB)) {
                 using QD = decltype(Q[0].d0);
-                if (delta0 && bc_plain<kBcGroupsDelta0>(gt))
+                if (delta0 && bc_plain<kBcGroupsDelta0>(gt)) {
                     bc_tile_compact<false, RB, kBcGroupsDelta0, QD, true>(rep.lat, c, t, gt, local,
                                                                           Q[threadIdx.x >> 6].d0, e);
-                else if (delta0)
+                } else if (delta0) {
                     bc_tile_compact<false, RB, kBcGroupsDelta0>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].d0, e);
-                else
+                } else if constexpr ((MODELS & kBatchBcGeneral) != 0) {
                     bc_tile_compact<false, RB, kBcGroups>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].gen, e);
+                }
             } else if (delta0 && bc_plain<kBcGroupsDelta0>(gt)) {
                 bc_tile<false, RB, kBcGroupsDelta0, true>(rep.lat, c, t, gt, local, e);
             } else if (delta0) {
                 bc_tile<false, RB, kBcGroupsDelta0>(rep.lat, c, t, gt, local, e);
-            } else {
+            } else if constexpr ((MODELS & kBatchBcGeneral) != 0) {
                 bc_tile<false, RB, kBcGroups>(rep.lat, c, t, gt, local, e);
             }
         }
@@ -138,10 +140,14 @@ hipError_t launch_batch_v(int models, const BatchReplica *reps, const uint32_t *
                           const GroupTable *tables, uint32_t stride, const uint32_t *step_base, uint32_t step,
                           uint32_t colour, hipStream_t st)
 {
+    constexpr int I = kBatchIsing, B = kBatchBc, G = kBatchBcGeneral;
     switch (models) {
-    case kBatchIsing: return launch_batch_vm<V, kBatchIsing>(reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
-    case kBatchBc: return launch_batch_vm<V, kBatchBc>(reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
-    case kBatchMixed: return launch_batch_vm<V, kBatchMixed>(reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
+    case I: return launch_batch_vm<V, I>(reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
+    case B: return launch_batch_vm<V, B>(reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
+    case I | B: return launch_batch_vm<V, I | B>(reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
+    case B | G: return launch_batch_vm<V, B | G>(reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
+    case I | B | G:
+        return launch_batch_vm<V, I | B | G>(reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -24,9 +24,11 @@ struct BatchReplica {
     uint64_t tile0;
 };
 
-// Models present in a batch (bit 0 Ising, bit 1 Blume-Capel): the batched
-// kernel is specialised on it.
-enum BatchModels : int { kBatchIsing = 1, kBatchBc = 2, kBatchMixed = 3 };
+// Models present in a batch: bit 0 Ising, bit 1 Blume-Capel, bit 2
+// Blume-Capel with Delta != 0 (13 acceptance groups; set only with bit 1).
+// The batched kernel is specialised on it, so a batch without the 13-group
+// replicas keeps their thresholds and masks out of its registers.
+enum BatchModels : int { kBatchIsing = 1, kBatchBc = 2, kBatchBcGeneral = 4 };
 // Batched half-sweep of colour c over a flat tile list of many lattices
 // (tile_rep: replica of each tile, laid out by the rows per thread of the
 // strategy pair).  The schedule step of a launch is *step_base + step

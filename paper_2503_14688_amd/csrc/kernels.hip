@@ -107,7 +107,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep_ising(Lattice lat, uint32_t c,
         block_reduce_atomic<kEmCounters>(e, acc);
 }
 
-template <bool MEASURE, int V>
+// One kernel per group count and classification form, so that each keeps
+// only its own thresholds and masks in registers (one kernel with both group
+// counts spills scalar registers in the loops of either).
+template <bool MEASURE, int V, int NG, bool PLAIN>
 __global__ __launch_bounds__(kBlock) void k_sweep_bc(Lattice lat, uint32_t c, uint32_t t, GroupTable gt,
                                                      unsigned long long *acc)
 {
@@ -115,27 +118,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep_bc(Lattice lat, uint32_t c, ui
     unsigned long long e[kEmCounters] = {0, 0, 0, 0};
     const uint64_t ntiles = tiles_of<R>(lat);
     if constexpr (variant_compact(V)) {
-        __shared__ BcListUnion<V> Q[kWaves];
-        using QD = decltype(Q[0].d0);
-        if (lat.bc_groups == kBcGroupsDelta0 && bc_plain<kBcGroupsDelta0>(gt)) {
-            for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-                bc_tile_compact<MEASURE, R, kBcGroupsDelta0, QD, true>(lat, c, t, gt, tile, Q[threadIdx.x >> 6].d0, e);
-        } else if (lat.bc_groups == kBcGroupsDelta0) {
-            for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-                bc_tile_compact<MEASURE, R, kBcGroupsDelta0>(lat, c, t, gt, tile, Q[threadIdx.x >> 6].d0, e);
-        } else {
-            for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-                bc_tile_compact<MEASURE, R, kBcGroups>(lat, c, t, gt, tile, Q[threadIdx.x >> 6].gen, e);
-        }
-    } else if (lat.bc_groups == kBcGroupsDelta0 && bc_plain<kBcGroupsDelta0>(gt)) {
+        using QB = BcList<NG, bc_list_cap(V), R>;
+        __shared__ QB Q[kWaves];
         for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-            bc_tile<MEASURE, R, kBcGroupsDelta0, true>(lat, c, t, gt, tile, e);
-    } else if (lat.bc_groups == kBcGroupsDelta0) {
-        for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-            bc_tile<MEASURE, R, kBcGroupsDelta0>(lat, c, t, gt, tile, e);
+            bc_tile_compact<MEASURE, R, NG, QB, PLAIN>(lat, c, t, gt, tile, Q[threadIdx.x >> 6], e);
     } else {
         for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-            bc_tile<MEASURE, R, kBcGroups>(lat, c, t, gt, tile, e);
+            bc_tile<MEASURE, R, NG, PLAIN>(lat, c, t, gt, tile, e);
     }
     if (MEASURE)
         block_reduce_atomic<kEmCounters>(e, acc);
@@ -335,8 +324,14 @@ hipError_t launch_half_sweep_v(const Lattice &lat, uint32_t colour, uint32_t t, 
                            t, gt, em_acc);
     } else {
         static const unsigned g = 65536u;
-        hipLaunchKernelGGL((k_sweep_bc<M, V>), dim3(g < tiles ? g : (unsigned)tiles), block, 0, st, lat, colour, t,
-                           gt, em_acc);
+        const dim3 grid(g < tiles ? g : (unsigned)tiles);
+        if (lat.bc_groups == kBcGroupsDelta0 && bc_plain<kBcGroupsDelta0>(gt))
+            hipLaunchKernelGGL((k_sweep_bc<M, V, kBcGroupsDelta0, true>), grid, block, 0, st, lat, colour, t, gt, em_acc);
+        else if (lat.bc_groups == kBcGroupsDelta0)
+            hipLaunchKernelGGL((k_sweep_bc<M, V, kBcGroupsDelta0, false>), grid, block, 0, st, lat, colour, t, gt,
+                               em_acc);
+        else
+            hipLaunchKernelGGL((k_sweep_bc<M, V, kBcGroups, false>), grid, block, 0, st, lat, colour, t, gt, em_acc);
     }
     return hipGetLastError();
 }

@@ -413,7 +413,7 @@ __device__ __forceinline__ void bc_classify(const GroupTable &gt, const Pair &s,
 // Every one of the NG groups draws random numbers and none is never accepted
 // (every finite T > 0): the classification then needs no selects.
 template <int NG>
-__device__ __forceinline__ bool bc_plain(const GroupTable &gt)
+__host__ __device__ __forceinline__ bool bc_plain(const GroupTable &gt)
 {
     constexpr uint32_t all = (1u << NG) - 1u;
     return (gt.rng_bits & all) == all && (gt.never_bits & all) == 0u;
@@ -681,17 +681,9 @@ __host__ __device__ inline uint64_t tiles_of(const Lattice &lat)
     return ((uint64_t)(lat.L / R) * lat.W + kBlock - 1) / kBlock;
 }
 
-// LDS of the compacting tiles, per wavefront: one list per model and group
-// count, sharing that wavefront's storage (a tile uses one of them).
 // Blume-Capel list slots per wavefront: 8 per row of the tile (about 6% of
 // the words are still undecided after eight planes).
 constexpr int bc_list_cap(int v) { return v == 4 ? 16 : 8 * variant_rows(v); }
-
-template <int V>
-union BcListUnion {
-    BcList<kBcGroupsDelta0, bc_list_cap(V), variant_rows(V)> d0;
-    BcList<kBcGroups, bc_list_cap(V), variant_rows(V)> gen;
-};
 
 } // namespace
 
