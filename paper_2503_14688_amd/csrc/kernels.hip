@@ -72,7 +72,10 @@ __global__ __launch_bounds__(kBlock) void k_init_bc(uint32_t *planes, uint32_t L
     }
 }
 
-template <bool MEASURE, int V>
+// One kernel per tile form: row-uniform or not (rows a multiple of 64
+// words), select-free classification or not, so that each keeps only its
+// own path's values in registers.
+template <bool MEASURE, int V, bool UNIFORM, bool PLAIN>
 __global__ __launch_bounds__(kBlock) void k_sweep_ising(Lattice lat, uint32_t c, uint32_t t, GroupTable gt,
                                                         unsigned long long *acc)
 {
@@ -80,28 +83,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep_ising(Lattice lat, uint32_t c,
     unsigned long long e[kEmCounters] = {0, 0, 0, 0};
     const uint64_t ntiles = tiles_of<R>(lat);
     if constexpr (variant_compact(V)) {
-        __shared__ WaveList<variant_list_cap(V)> Q[kWaves];
         using QL = WaveList<variant_list_cap(V)>;
-        const bool plain = (gt.rng_bits & 3u) == 3u && (gt.never_bits & 3u) == 0u;
-        if (lat.W % 64 == 0 && plain) {
-            for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-                ising_tile_compact<MEASURE, R, true, QL, true>(lat, c, t, gt, tile, Q[threadIdx.x >> 6], e);
-        } else if (lat.W % 64 == 0) {
-            for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-                ising_tile_compact<MEASURE, R, true>(lat, c, t, gt, tile, Q[threadIdx.x >> 6], e);
-        } else if (plain) {
-            for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-                ising_tile_compact<MEASURE, R, false, QL, true>(lat, c, t, gt, tile, Q[threadIdx.x >> 6], e);
-        } else {
-            for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-                ising_tile_compact<MEASURE, R, false>(lat, c, t, gt, tile, Q[threadIdx.x >> 6], e);
-        }
-    } else if (lat.W % 64 == 0) {
+        __shared__ QL Q[kWaves];
         for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-            ising_tile_lazy<MEASURE, R, true>(lat, c, t, gt, tile, e);
+            ising_tile_compact<MEASURE, R, UNIFORM, QL, PLAIN>(lat, c, t, gt, tile, Q[threadIdx.x >> 6], e);
     } else {
         for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-            ising_tile_lazy<MEASURE, R, false>(lat, c, t, gt, tile, e);
+            ising_tile_lazy<MEASURE, R, UNIFORM>(lat, c, t, gt, tile, e);
     }
     if (MEASURE)
         block_reduce_atomic<kEmCounters>(e, acc);
@@ -320,8 +308,20 @@ hipError_t launch_half_sweep_v(const Lattice &lat, uint32_t colour, uint32_t t, 
     // while a block's grid-stride loop walks its tiles
     if (lat.model == kIsing) {
         static const unsigned g = 65536u;
-        hipLaunchKernelGGL((k_sweep_ising<M, V>), dim3(g < tiles ? g : (unsigned)tiles), block, 0, st, lat, colour,
-                           t, gt, em_acc);
+        const dim3 grid(g < tiles ? g : (unsigned)tiles);
+        const bool uniform = lat.W % 64 == 0;
+        // the select-free classification matters for the compacting tiles only
+        const bool plain = variant_compact(V) && (gt.rng_bits & 3u) == 3u && (gt.never_bits & 3u) == 0u;
+        if (uniform && plain)
+            hipLaunchKernelGGL((k_sweep_ising<M, V, true, variant_compact(V)>), grid, block, 0, st, lat, colour, t, gt,
+                               em_acc);
+        else if (uniform)
+            hipLaunchKernelGGL((k_sweep_ising<M, V, true, false>), grid, block, 0, st, lat, colour, t, gt, em_acc);
+        else if (plain)
+            hipLaunchKernelGGL((k_sweep_ising<M, V, false, variant_compact(V)>), grid, block, 0, st, lat, colour, t,
+                               gt, em_acc);
+        else
+            hipLaunchKernelGGL((k_sweep_ising<M, V, false, false>), grid, block, 0, st, lat, colour, t, gt, em_acc);
     } else {
         static const unsigned g = 65536u;
         const dim3 grid(g < tiles ? g : (unsigned)tiles);
