@@ -34,8 +34,69 @@ __device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k)
 
 // One Philox4x32-10 block.  The key (k0, k1) must be uniform across the
 // wavefront: the round keys live in scalar registers.
+//
+// The sweep index and stream tag (words 2 and 3) are wave-uniform at every
+// call, so the first two rounds are plain C, grouped so that the compiler
+// combines their uniform parts in scalar registers (one vector XOR each
+// instead of a register copy and a three-input XOR); from round 3 on every
+// word is per lane.
 __device__ __forceinline__ Block4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                 uint32_t k0, uint32_t k1)
+{
+    k0 = __builtin_amdgcn_readfirstlane(k0);
+    k1 = __builtin_amdgcn_readfirstlane(k1);
+    uint64_t p0, p1;
+    uint32_t n0, n2;
+    // round 1: words 2 and 3 uniform, so are the product of word 2 and the
+    // key parts XORed with them
+    p0 = (uint64_t)kPhiloxM0 * c0;
+    p1 = (uint64_t)kPhiloxM1 * c2;
+    n0 = ((uint32_t)(p1 >> 32) ^ k0) ^ c1;
+    n2 = (uint32_t)(p0 >> 32) ^ (c3 ^ k1);
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+    // round 2: word 1 (the low half of round 1's uniform product) uniform
+    p0 = (uint64_t)kPhiloxM0 * c0;
+    p1 = (uint64_t)kPhiloxM1 * c2;
+    n0 = (uint32_t)(p1 >> 32) ^ (c1 ^ k0);
+    n2 = xor3_key((uint32_t)(p0 >> 32), c3, k1);
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+#pragma unroll
+    for (int round = 2; round < 10; ++round) {
+        p0 = (uint64_t)kPhiloxM0 * c0;
+        p1 = (uint64_t)kPhiloxM1 * c2;
+        n0 = xor3_key((uint32_t)(p1 >> 32), c1, k0);
+        n2 = xor3_key((uint32_t)(p0 >> 32), c3, k1);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+    Block4 r;
+    r.v[0] = c0;
+    r.v[1] = c1;
+    r.v[2] = c2;
+    r.v[3] = c3;
+    return r;
+}
+
+// philox4x32_10 with every round on the vector unit (the scalar unit only
+// bumps the round keys).  For the per-word two-group test on row-uniform
+// counters, where the form above would put most of the first two rounds on
+// the scalar unit and make it the busier one (measured 3-4% slower there).
+__device__ __forceinline__ Block4 philox4x32_10_vec(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                    uint32_t k0, uint32_t k1)
 {
     k0 = __builtin_amdgcn_readfirstlane(k0);
     k1 = __builtin_amdgcn_readfirstlane(k1);
@@ -239,7 +300,9 @@ __device__ __forceinline__ uint32_t metropolis_accept(const uint32_t (&need)[NG]
         undecided |= need[g];
     uint32_t accepted = always;
     for (uint32_t blk = 0; blk < 8u && undecided != 0u; ++blk) {
-        const Block4 r = philox4x32_10(row, word, t, stream_tag(kPurposeAccept, colour, blk), k0, k1);
+        const uint32_t tag = stream_tag(kPurposeAccept, colour, blk);
+        const Block4 r = NG == 2 ? philox4x32_10_vec(row, word, t, tag, k0, k1)
+                                 : philox4x32_10(row, word, t, tag, k0, k1);
         apply_block<NG>(r, blk, need, thr, undecided, accepted);
     }
     return accepted;
