@@ -17,6 +17,11 @@ OUT = os.path.join(HERE, "libspin.so")
 SOURCES = ["kernels.hip", "batch_kernels.hip", "corr.hip", "spin.hip", "batch.hip", "measure_noalloc.hip", "cluster.hip",
            "equilibrium.hip"]
 ARCH = "gfx950"
+# The sweep kernels branch on wave-uniform values (per-plane threshold
+# patterns of the Blume-Capel groups); left unstructured, such regions are
+# plain scalar compare-and-branch trees instead of flag-merged ones.
+SOURCE_FLAGS = {src: ["-mllvm", "-structurizecfg-skip-uniform-regions"]
+                for src in ("kernels.hip", "batch_kernels.hip")}
 
 
 def hipcc() -> str:
@@ -35,7 +40,7 @@ def build(verbose: bool = False) -> str:
     objs, cmds = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmds.append([hipcc(), *flags(), "-c", os.path.join(CSRC, src), "-o", obj])
+        cmds.append([hipcc(), *flags(), *SOURCE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     # the sources compile independently: a few at a time
     jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))

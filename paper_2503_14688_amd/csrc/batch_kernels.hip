@@ -64,7 +64,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica 
         // keys and the row-uniform Philox rounds stay scalar.
         const uint32_t rid = __builtin_amdgcn_readfirstlane(tile_rep[tile]);
         const BatchReplica rep = wave_uniform_copy(reps + rid);
-        const GroupTable gt = wave_uniform_copy(tables + (size_t)rep.sched * stride + step);
+        const GroupTable *gtp = tables + (size_t)rep.sched * stride + step;
+        const GroupTable gt = wave_uniform_copy(gtp);
+        const uint32_t *pats = gtp->plane_groups;
         const uint64_t local = tile - rep.tile0;
         const uint32_t t = rep.t0 + step;
         if (rep.lat.model == kIsing) {
@@ -93,19 +95,19 @@ __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica 
             if constexpr (variant_compact(VB)) {
                 using QD = decltype(Q[0].d0);
                 if (delta0 && bc_plain<kBcGroupsDelta0>(gt)) {
-                    bc_tile_compact<false, RB, kBcGroupsDelta0, QD, true>(rep.lat, c, t, gt, local,
+                    bc_tile_compact<false, RB, kBcGroupsDelta0, QD, true>(rep.lat, c, t, gt, pats, local,
                                                                           Q[threadIdx.x >> 6].d0, e);
                 } else if (delta0) {
-                    bc_tile_compact<false, RB, kBcGroupsDelta0>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].d0, e);
+                    bc_tile_compact<false, RB, kBcGroupsDelta0>(rep.lat, c, t, gt, pats, local, Q[threadIdx.x >> 6].d0, e);
                 } else if constexpr ((MODELS & kBatchBcGeneral) != 0) {
-                    bc_tile_compact<false, RB, kBcGroups>(rep.lat, c, t, gt, local, Q[threadIdx.x >> 6].gen, e);
+                    bc_tile_compact<false, RB, kBcGroups>(rep.lat, c, t, gt, pats, local, Q[threadIdx.x >> 6].gen, e);
                 }
             } else if (delta0 && bc_plain<kBcGroupsDelta0>(gt)) {
-                bc_tile<false, RB, kBcGroupsDelta0, true>(rep.lat, c, t, gt, local, e);
+                bc_tile<false, RB, kBcGroupsDelta0, true>(rep.lat, c, t, gt, pats, local, e);
             } else if (delta0) {
-                bc_tile<false, RB, kBcGroupsDelta0>(rep.lat, c, t, gt, local, e);
+                bc_tile<false, RB, kBcGroupsDelta0>(rep.lat, c, t, gt, pats, local, e);
             } else if constexpr ((MODELS & kBatchBcGeneral) != 0) {
-                bc_tile<false, RB, kBcGroups>(rep.lat, c, t, gt, local, e);
+                bc_tile<false, RB, kBcGroups>(rep.lat, c, t, gt, pats, local, e);
             }
         }
     }

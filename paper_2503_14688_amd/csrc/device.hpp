@@ -289,10 +289,132 @@ __device__ __forceinline__ void apply_block(const Block4 &r, uint32_t blk, const
     }
 }
 
+// Six-group form of apply_block (Blume-Capel at Delta = 0).  pat4 holds the
+// plane's group pattern byte by byte (bit g of byte q: group g's threshold
+// bit in plane 4 blk + q is 1).  A wave-uniform switch over the 64 patterns
+// gives each its own code: the threshold word is the OR of just the groups
+// in the pattern (none, one register, or one or two three-input ORs), fed
+// straight into the two three-input updates, so no copy or per-group test
+// runs on the vector unit.
+// The ORs are volatile: they must stay inside their case (the masks are the
+// same for every block of a word, and the compiler would otherwise compute
+// every case's OR once per word, ahead of the block loop).
+__device__ __forceinline__ uint32_t or2_here(uint32_t a, uint32_t b)
+{
+    uint32_t d;
+    asm volatile("v_or_b32 %0, %1, %2" : "=v"(d) : "v"(a), "v"(b));
+    return d;
+}
+
+__device__ __forceinline__ uint32_t or3_here(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t d;
+    asm volatile("v_or3_b32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
+// t | need[g] over the groups g in M (M != 0), two more groups per
+// three-input OR.
+template <uint32_t M>
+__device__ __forceinline__ uint32_t or_more(uint32_t t, const uint32_t (&need)[6])
+{
+    constexpr int a = __builtin_ctz(M);
+    constexpr uint32_t M1 = M & (M - 1u);
+    if constexpr (M1 == 0u) {
+        return or2_here(t, need[a]);
+    } else {
+        constexpr int b = __builtin_ctz(M1);
+        constexpr uint32_t M2 = M1 & (M1 - 1u);
+        const uint32_t r = or3_here(t, need[a], need[b]);
+        if constexpr (M2 == 0u)
+            return r;
+        else
+            return or_more<M2>(r, need);
+    }
+}
+
+// OR of need[g] over the groups g in M (M != 0): the register itself for
+// one group, else as few two- and three-input ORs as the count allows.
+template <uint32_t M>
+__device__ __forceinline__ uint32_t or_groups(const uint32_t (&need)[6])
+{
+    constexpr int a = __builtin_ctz(M);
+    constexpr uint32_t M1 = M & (M - 1u);
+    if constexpr (M1 == 0u) {
+        return need[a];
+    } else {
+        constexpr int b = __builtin_ctz(M1);
+        constexpr uint32_t M2 = M1 & (M1 - 1u);
+        if constexpr (M2 == 0u) {
+            return or2_here(need[a], need[b]);
+        } else {
+            constexpr int c = __builtin_ctz(M2);
+            constexpr uint32_t M3 = M2 & (M2 - 1u);
+            const uint32_t r = or3_here(need[a], need[b], need[c]);
+            if constexpr (M3 == 0u)
+                return r;
+            else
+                return or_more<M3>(r, need);
+        }
+    }
+}
+
+template <uint32_t M>
+__device__ __forceinline__ void plane6(const uint32_t (&need)[6], uint32_t u, uint32_t &und, uint32_t &newly)
+{
+    if constexpr (M == 0u) {
+        newly = 0u;
+        und &= ~u;
+    } else {
+        const uint32_t tb = or_groups<M>(need);
+        newly = newly_accepted(und, tb, u);
+        und = still_tied(und, tb, u);
+    }
+}
+
+__device__ __forceinline__ void plane6_switch(uint32_t m, const uint32_t (&need)[6], uint32_t u, uint32_t &und,
+                                              uint32_t &newly)
+{
+#define SPIN_P1(n) case n: plane6<n>(need, u, und, newly); break;
+#define SPIN_P4(n) SPIN_P1(n) SPIN_P1(n + 1) SPIN_P1(n + 2) SPIN_P1(n + 3)
+#define SPIN_P16(n) SPIN_P4(n) SPIN_P4(n + 4) SPIN_P4(n + 8) SPIN_P4(n + 12)
+    switch (m) {
+        SPIN_P16(0u) SPIN_P16(16u) SPIN_P16(32u) SPIN_P16(48u)
+    default: break;
+    }
+#undef SPIN_P16
+#undef SPIN_P4
+#undef SPIN_P1
+}
+
+__device__ __forceinline__ void apply_block6(const Block4 &r, uint32_t pat4, const uint32_t (&need)[6],
+                                             uint32_t &undecided, uint32_t &accepted)
+{
+    uint32_t n[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        plane6_switch((pat4 >> (8 * q)) & 63u, need, r.v[q], undecided, n[q]);
+    accepted |= (n[0] | n[1]) | (n[2] | n[3]);
+}
+
+// apply_block for any group count; the six-group form reads its plane
+// patterns from pats (GroupTable::plane_groups, uniform).
+template <int NG>
+__device__ __forceinline__ void apply_block_any(const Block4 &r, uint32_t blk, const uint32_t (&need)[NG],
+                                                const uint32_t (&thr)[NG], const uint32_t *pats,
+                                                uint32_t &undecided, uint32_t &accepted)
+{
+    if constexpr (NG == 6)
+        apply_block6(r, __builtin_amdgcn_readfirstlane(pats[blk]), need, undecided, accepted);
+    else
+        apply_block<NG>(r, blk, need, thr, undecided, accepted);
+}
+
 template <int NG>
 __device__ __forceinline__ uint32_t metropolis_accept(const uint32_t (&need)[NG], const uint32_t (&thr)[NG],
                                                       uint32_t always, uint32_t row, uint32_t word,
-                                                      uint32_t t, uint32_t colour, uint32_t k0, uint32_t k1)
+                                                      uint32_t t, uint32_t colour, uint32_t k0, uint32_t k1,
+                                                      const uint32_t *pats = nullptr)
 {
     uint32_t undecided = 0;
 #pragma unroll
@@ -303,7 +425,7 @@ __device__ __forceinline__ uint32_t metropolis_accept(const uint32_t (&need)[NG]
         const uint32_t tag = stream_tag(kPurposeAccept, colour, blk);
         const Block4 r = NG == 2 ? philox4x32_10_vec(row, word, t, tag, k0, k1)
                                  : philox4x32_10(row, word, t, tag, k0, k1);
-        apply_block<NG>(r, blk, need, thr, undecided, accepted);
+        apply_block_any<NG>(r, blk, need, thr, pats, undecided, accepted);
     }
     return accepted;
 }

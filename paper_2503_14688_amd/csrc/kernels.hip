@@ -109,10 +109,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep_bc(Lattice lat, uint32_t c, ui
         using QB = BcList<NG, bc_list_cap(V), R>;
         __shared__ QB Q[kWaves];
         for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-            bc_tile_compact<MEASURE, R, NG, QB, PLAIN>(lat, c, t, gt, tile, Q[threadIdx.x >> 6], e);
+            bc_tile_compact<MEASURE, R, NG, QB, PLAIN>(lat, c, t, gt, gt.plane_groups, tile, Q[threadIdx.x >> 6], e);
     } else {
         for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-            bc_tile<MEASURE, R, NG, PLAIN>(lat, c, t, gt, tile, e);
+            bc_tile<MEASURE, R, NG, PLAIN>(lat, c, t, gt, gt.plane_groups, tile, e);
     }
     if (MEASURE)
         block_reduce_atomic<kEmCounters>(e, acc);

@@ -27,6 +27,10 @@ struct GroupTable {
     uint32_t never_bits;        // bit g: group g is never accepted (T = 0)
     uint32_t sel_a_bits;        // Blume-Capel: bit v (y = v - 4): the group's
                                 // positive family is s -> 0 (else 0 -> s')
+    // Threshold bits of groups 0..7 plane by plane: byte q of word b has bit
+    // g set when bit 31 - (4 b + q) of thr[g] is set (the groups whose
+    // threshold bit is 1 in plane 4 b + q).  Used by the six-group test.
+    uint32_t plane_groups[8];
 };
 
 struct Lattice {

@@ -112,6 +112,17 @@ bool merged_groups(double J, double Delta, double T, GroupTable &gt)
 
 // Group tables as the kernels consume them (see kernels.hpp): bc_groups is
 // the lattice's Blume-Capel group layout (13 general, 6 for Delta = 0).
+// Plane-by-plane threshold bits of groups 0..7 (GroupTable::plane_groups).
+void fill_plane_groups(GroupTable &gt)
+{
+    for (uint32_t k = 0; k < 32; ++k) {
+        uint32_t pat = 0;
+        for (uint32_t g = 0; g < 8; ++g)
+            pat |= ((gt.thr[g] >> (31u - k)) & 1u) << g;
+        gt.plane_groups[k / 4] |= pat << (8u * (k % 4));
+    }
+}
+
 GroupTable make_groups(int model, uint32_t bc_groups, double J, double Delta, double T)
 {
     GroupTable gt;
@@ -119,6 +130,7 @@ GroupTable make_groups(int model, uint32_t bc_groups, double J, double Delta, do
     uint32_t thr;
     if (model == SPIN_BLUME_CAPEL && bc_groups == spin::kBcGroupsDelta0) {
         merged_groups(J, Delta, T, gt);  // exactness checked when the layout was chosen
+        fill_plane_groups(gt);
         return gt;
     }
     if (model == SPIN_ISING) {

@@ -467,9 +467,11 @@ __device__ __forceinline__ void bc_nbrs(const uint32_t *oth, uint32_t L, uint32_
 // Blume-Capel half-sweep of one tile, one word at a time: each thread runs
 // the lazy Metropolis test of its word to completion.  Each row loads the
 // next row's words before it draws random planes.
+// pats: the table's plane_groups, read with uniform loads (the kernel
+// argument's, or the batch table's in global memory).
 template <bool MEASURE, int R, int NG, bool PLAIN = false>
 __device__ __forceinline__ void bc_tile(const Lattice &lat, uint32_t c, uint32_t t, const GroupTable &gt,
-                                        uint64_t tile, unsigned long long (&e)[kEmCounters])
+                                        const uint32_t *pats, uint64_t tile, unsigned long long (&e)[kEmCounters])
 {
     const uint32_t L = lat.L, W = lat.W;
     uint32_t *own = lat.planes + (c ? lat.plane_u32 : 0);
@@ -512,7 +514,7 @@ __device__ __forceinline__ void bc_tile(const Lattice &lat, uint32_t c, uint32_t
 #pragma unroll
         for (int q = 0; q < NG; ++q)
             any |= need[q];
-        const uint32_t F = metropolis_accept<NG>(need, thr, ~(any | never), i, w, t, c, lat.key0, lat.key1);
+        const uint32_t F = metropolis_accept<NG>(need, thr, ~(any | never), i, w, t, c, lat.key0, lat.key1, pats);
         const Pair n = bc_new_state(F, s, X);
         bc_store(own, (size_t)i * W + w, n);
         if (MEASURE)
@@ -543,7 +545,8 @@ struct BcList {
 
 template <bool MEASURE, int R, int NG, typename List, bool PLAIN = false>
 __device__ __forceinline__ void bc_tile_compact(const Lattice &lat, uint32_t c, uint32_t t, const GroupTable &gt,
-                                                uint64_t tile, List &Q, unsigned long long (&e)[kEmCounters])
+                                                const uint32_t *pats, uint64_t tile, List &Q,
+                                                unsigned long long (&e)[kEmCounters])
 {
     constexpr int kListCap = List::kCap;
     const uint32_t L = lat.L, W = lat.W;
@@ -599,11 +602,11 @@ __device__ __forceinline__ void bc_tile_compact(const Lattice &lat, uint32_t c, 
             acc = ~(und | never);
             if (und != 0u) {
                 const Block4 b = philox4x32_10(i, w, t, stream_tag(kPurposeAccept, c, 0), k0, k1);
-                apply_block<NG>(b, 0u, need, thr, und, acc);
+                apply_block_any<NG>(b, 0u, need, thr, pats, und, acc);
             }
             if (und != 0u) {
                 const Block4 b = philox4x32_10(i, w, t, stream_tag(kPurposeAccept, c, 1), k0, k1);
-                apply_block<NG>(b, 1u, need, thr, und, acc);
+                apply_block_any<NG>(b, 1u, need, thr, pats, und, acc);
             }
         }
         const unsigned long long bal = __ballot(und != 0u);
@@ -624,7 +627,7 @@ __device__ __forceinline__ void bc_tile_compact(const Lattice &lat, uint32_t c, 
             } else {
                 for (uint32_t blk = 2; blk < 8u && und != 0u; ++blk) {
                     const Block4 b = philox4x32_10(i, w, t, stream_tag(kPurposeAccept, c, blk), k0, k1);
-                    apply_block<NG>(b, blk, need, thr, und, acc);
+                    apply_block_any<NG>(b, blk, need, thr, pats, und, acc);
                 }
             }
         }
@@ -654,7 +657,7 @@ __device__ __forceinline__ void bc_tile_compact(const Lattice &lat, uint32_t c, 
         uint32_t und = Q.und[k], acc = Q.acc[k];
         for (uint32_t blk = 2; blk < 8u && und != 0u; ++blk) {
             const Block4 b = philox4x32_10(i, wq, t, stream_tag(kPurposeAccept, c, blk), k0, k1);
-            apply_block<NG>(b, blk, need, thr, und, acc);
+            apply_block_any<NG>(b, blk, need, thr, pats, und, acc);
         }
         const uint2 old = Q.stage[slot >> 6][owner];
         const Pair ns = bc_new_state(acc, Pair{old.x, old.y}, Q.x[k]);
