@@ -270,12 +270,12 @@ typedef struct spin_replica_desc {
  * capturing a graph; SPIN_BATCH_VARIANT(v) forces batched strategy v,
  * 0 <= v < SPIN_BATCH_VARIANTS, instead of the tuned one.  A batched strategy
  * is a pair of sweep strategies (see spin_set_variant), one for the Ising and
- * one for the Blume-Capel replicas: v = 0..4 runs strategy v for both; 5, 6
- * and 7 run (Ising, Blume-Capel) = (2, 0), (2, 3) and (1, 3).  Every strategy
- * gives the same lattices. */
+ * one for the Blume-Capel replicas: v = 0..4 runs strategy v for both; 5, 6,
+ * 7 and 8 run (Ising, Blume-Capel) = (2, 0), (2, 3), (1, 3) and (2, 1).
+ * Every strategy gives the same lattices. */
 #define SPIN_BATCH_DIRECT 1u
 #define SPIN_BATCH_VARIANT(v) ((uint32_t)((v) + 1) << 4)
-#define SPIN_BATCH_VARIANTS 8
+#define SPIN_BATCH_VARIANTS 9
 
 /* Create a batch of n replicas.  T holds n_sched schedules of
  * n_steps temperatures each: T[s * n_steps + k] is the bath temperature of

@@ -45,13 +45,13 @@ class spin_fourier(ctypes.Structure):
 BATCH_DIRECT = 1
 
 
-BATCH_VARIANTS = 8  # batched strategies: (Ising, Blume-Capel) sweep strategy pairs
+BATCH_VARIANTS = 9  # batched strategies: (Ising, Blume-Capel) sweep strategy pairs
 
 
 def BATCH_VARIANT(v):
     """spin_batch_run flag forcing batched strategy v (0 <= v < BATCH_VARIANTS):
     sweep strategy v for both models for v < 5, else the (Ising, Blume-Capel)
-    pair (2, 0), (2, 3) or (1, 3)."""
+    pair (2, 0), (2, 3), (1, 3) or (2, 1)."""
     if not 0 <= v < BATCH_VARIANTS:
         raise ValueError(f"batched strategy {v} outside 0..{BATCH_VARIANTS - 1}")
     return (v + 1) << 4

@@ -17,11 +17,12 @@ OUT = os.path.join(HERE, "libspin.so")
 SOURCES = ["kernels.hip", "batch_kernels.hip", "corr.hip", "spin.hip", "batch.hip", "measure_noalloc.hip", "cluster.hip",
            "equilibrium.hip"]
 ARCH = "gfx950"
-# The sweep kernels branch on wave-uniform values (per-plane threshold
-# patterns of the Blume-Capel groups); left unstructured, such regions are
-# plain scalar compare-and-branch trees instead of flag-merged ones.
+# The kernels branch on wave-uniform values (per-plane threshold patterns of
+# the Blume-Capel groups, separation groups of the correlation sums); left
+# unstructured, such regions are plain scalar compare-and-branch trees
+# instead of flag-merged ones.
 SOURCE_FLAGS = {src: ["-mllvm", "-structurizecfg-skip-uniform-regions"]
-                for src in ("kernels.hip", "batch_kernels.hip")}
+                for src in ("kernels.hip", "batch_kernels.hip", "corr.hip", "cluster.hip")}
 
 
 def hipcc() -> str:

@@ -167,6 +167,7 @@ hipError_t launch_batch_half_sweep(int variant, int models, const BatchReplica *
     case 5: return launch_batch_v<5>(models, reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
     case 6: return launch_batch_v<6>(models, reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
     case 7: return launch_batch_v<7>(models, reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
+    case 8: return launch_batch_v<8>(models, reps, tile_rep, ntiles, tables, stride, step_base, step, colour, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -8,12 +8,12 @@ namespace spin {
 
 // Strategies of the batched kernel: one sweep strategy for the Ising tiles
 // and one for the Blume-Capel tiles of the same launch.  0..4 use strategy v
-// for both models; 5..7 pair a compacting Ising tile with a per-word
-// Blume-Capel one (the best single-lattice pairing): 5 = (2, 0), 6 = (2, 3),
-// 7 = (1, 3) as (Ising strategy, Blume-Capel strategy).
-constexpr int kBatchVariants = 8;
+// for both models; 5..8 pair the compacting Ising tile with another
+// Blume-Capel one: 5 = (2, 0), 6 = (2, 3), 7 = (1, 3), 8 = (2, 1) as
+// (Ising strategy, Blume-Capel strategy).
+constexpr int kBatchVariants = 9;
 __host__ __device__ constexpr int batch_ising_variant(int bv) { return bv < 5 ? bv : (bv == 7 ? 1 : 2); }
-__host__ __device__ constexpr int batch_bc_variant(int bv) { return bv < 5 ? bv : (bv == 5 ? 0 : 3); }
+__host__ __device__ constexpr int batch_bc_variant(int bv) { return bv < 5 ? bv : (bv == 5 ? 0 : bv == 8 ? 1 : 3); }
 
 // One replica of a batch: its lattice, its schedule and its first tile in
 // the batch's flat tile list.

@@ -117,7 +117,7 @@ def test_many_tiles_per_block_mixed_models(gpu):
         solo.sweep(T[rep["schedule"]])
         want.append(solo.spins())
         solo.close()
-    for v in (1, 2, 4, 5, 6, 7):
+    for v in (1, 2, 4, 5, 6, 7, 8):
         b = gpu.Batch(reps, T).init_random()
         b.run(n, gpu.BATCH_VARIANT(v))
         b.sync()
