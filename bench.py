@@ -38,16 +38,18 @@ SWEEP_SOURCES = ["paper_2503_14688_amd/csrc/kernels.hip", "paper_2503_14688_amd/
                  "paper_2503_14688_amd/csrc/device.hpp", "paper_2503_14688_amd/csrc/kernels.hpp"]
 MEASURED_TRAFFIC = {
     # (workload, sweep strategy): bytes per launch
-    ("ising_L1048576_tc", 2): 221.55e9,
-    ("bc_L262144_t16937", 0): 27.76e9,
+    ("ising_L1048576_tc", 2): 221.68e9,
+    ("bc_L262144_t16937", 0): 28.50e9,
+    ("bc_L262144_t16937", 1): 26.88e9,
 }
-MEASURED_WITH = "3f3924b864c7cda5"
+MEASURED_WITH = "e7f3277c3fa33ba3"
 # (workload, sweep strategy): wave instructions per 64 words of a colour plane
 # (SQ_INSTS_VALU, SQ_INSTS_SALU) and the clock (GHz, GRBM_GUI_ACTIVE over the
 # dispatch) from the same counter pass
 MEASURED_ISSUE = {
-    ("ising_L1048576_tc", 2): (139.7, 95.8, 2.16),
-    ("bc_L262144_t16937", 0): (352.4, 234.3, 2.33),
+    ("ising_L1048576_tc", 2): (138.3, 93.0, 2.14),
+    ("bc_L262144_t16937", 0): (292.4, 159.3, 2.16),
+    ("bc_L262144_t16937", 1): (280.3, 139.1, 2.11),
 }
 
 
