@@ -415,8 +415,12 @@ __device__ __forceinline__ Row8 y_row(const uint32_t *ring, int jr, uint32_t slo
     uint32_t base = slot0 + RING - (r % RING);
     if (base >= RING)
         base -= RING;
-    base = __builtin_amdgcn_readfirstlane(base);
-    return lds_row(ring + ring_index(bl + (uint32_t)jr) + (base - bl) * kRingCols);
+    // the whole scalar part in one scalar register (base >= bl: base % 16 ==
+    // bl), so the lane's address is one vector add and both 16-byte halves
+    // are reached by non-negative immediate offsets of the LDS loads
+    uint32_t sb = (base - bl) * kRingCols;
+    asm("" : "+s"(sb));  // keeps the constant part inside the scalar
+    return lds_row(ring + ring_index(bl + (uint32_t)jr) + sb);
 }
 
 // Counts of one pair, added to the running counters (b: base row j - r,
