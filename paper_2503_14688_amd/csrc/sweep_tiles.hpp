@@ -133,12 +133,12 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
     const uint32_t k0 = lat.key0, k1 = lat.key1;
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t g = tile * kBlock + threadIdx.x;
-    const bool valid = g < nitems;
+    // W % 64 == 0 makes L a multiple of 4096, so the items fill whole tiles:
+    // with UNIFORM no lane is past the end, and the test is compiled out
+    const bool valid = UNIFORM || g < nitems;
     uint32_t rg, w;
     if (UNIFORM) {
-        // W % 64 == 0: the wavefront's 64 items lie in one row group (and L is
-        // a multiple of 4096, so the items fill whole tiles: no lane is past
-        // the end)
+        // W % 64 == 0: the wavefront's 64 items lie in one row group
         const uint32_t wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) & ~63u;
         rg = __builtin_amdgcn_readfirstlane((uint32_t)((tile * kBlock + wave0) / W));
         w = (uint32_t)(g - (uint64_t)rg * W);
@@ -278,7 +278,7 @@ __device__ __forceinline__ void ising_tile_lazy(const Lattice &lat, uint32_t c, 
     const uint32_t *oth = lat.planes + (c ? 0 : lat.plane_u32);
     const uint64_t nitems = (uint64_t)(L / R) * W;
     const uint64_t g = tile * kBlock + threadIdx.x;
-    if (g >= nitems)
+    if (!UNIFORM && g >= nitems)  // UNIFORM: whole tiles (see ising_tile_compact)
         return;
     const uint32_t thr[2] = {gt.thr[0], gt.thr[1]};
     const bool rng3 = gt.rng_bits & 1u, rng4 = gt.rng_bits & 2u;
