@@ -175,8 +175,11 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
         }
         const uint32_t odd = (i + c) & 1u;
         const uint32_t side = side_word(cur, nbw, odd);
-        uint32_t acc = 0, und = 0, need[2] = {0u, 0u};
-        if (valid) {
+        // every lane runs the word it holds (lanes past the end hold words that
+        // exist and drop out with an empty undecided set afterwards), so no
+        // lane state needs zeroing first
+        uint32_t acc, und, need[2];
+        {
             // aligned-neighbour indicators; a = number aligned, dE = J (4a - 8)
             const uint32_t e1 = ~(sv ^ up), e2 = ~(sv ^ dn), e3 = ~(sv ^ cur), e4 = ~(sv ^ side);
             const uint32_t a1 = e1 & e2, x1 = e1 ^ e2, a2 = e3 & e4, x2 = e3 ^ e4;
@@ -200,6 +203,7 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
             apply_block_2g_pm<0>(b0, pm, need[1], und, acc);
             const Block4 b1 = philox_block<UNIFORM>(i, w, t, stream_tag(kPurposeAccept, c, 1), k0, k1);
             apply_block_2g_pm<1>(b1, pm, need[1], und, acc);
+            und = valid ? und : 0u;
         }
         const unsigned long long bal = __ballot(und != 0u);
         bool listed = false;
