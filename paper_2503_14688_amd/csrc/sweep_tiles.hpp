@@ -363,44 +363,61 @@ template <int NG, bool PLAIN = false>
 __device__ __forceinline__ void bc_classify(const GroupTable &gt, const Pair &s, const Pair (&nbr)[4], uint32_t X,
                                             uint32_t (&need)[NG], uint32_t &never)
 {
-    // sign carried by y: that of s when s != 0, of the proposed s' when s = 0
-    const uint32_t neg = (s.z & s.s) | (~s.z & X);
-    uint32_t bits[8];
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-        const uint32_t anti = nbr[n].s ^ neg;
-        bits[n] = nbr[n].z & ~anti;        // neighbour contributes +1 to y
-        bits[4 + n] = ~(nbr[n].z & anti);  // neighbour does not contribute -1
-    }
-    uint32_t b0, b1, b2, b3;
-    count8(bits, b0, b1, b2, b3);  // v = y + 4 in [0, 8]
-    uint32_t Y[9];
-    {
-        const uint32_t nb3 = ~b3;
-        const uint32_t t0 = ~b1 & ~b0, t1 = ~b1 & b0, t2 = b1 & ~b0, t3 = b1 & b0;
-        const uint32_t h0 = nb3 & ~b2, h1 = nb3 & b2;
-        Y[0] = h0 & t0; Y[1] = h0 & t1; Y[2] = h0 & t2; Y[3] = h0 & t3;
-        Y[4] = h1 & t0; Y[5] = h1 & t1; Y[6] = h1 & t2; Y[7] = h1 & t3;
-        Y[8] = b3;
-    }
-    const uint32_t famA = s.z & ~X;  // s -> 0:   dE = J y - Delta
-    const uint32_t famB = ~s.z;      // 0 -> s':  dE = -J y + Delta
-    const uint32_t famC = s.z & X;   // s -> -s:  dE = 2 J y
     uint32_t mask[NG];
     if constexpr (NG == kBcGroups) {
+        // sign carried by y: that of s when s != 0, of the proposed s' when s = 0
+        const uint32_t neg = (s.z & s.s) | (~s.z & X);
+        uint32_t bits[8];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const uint32_t anti = nbr[n].s ^ neg;
+            bits[n] = nbr[n].z & ~anti;        // neighbour contributes +1 to y
+            bits[4 + n] = ~(nbr[n].z & anti);  // neighbour does not contribute -1
+        }
+        uint32_t b0, b1, b2, b3;
+        count8(bits, b0, b1, b2, b3);  // v = y + 4 in [0, 8]
+        uint32_t Y[9];
+        {
+            const uint32_t nb3 = ~b3;
+            const uint32_t t0 = ~b1 & ~b0, t1 = ~b1 & b0, t2 = b1 & ~b0, t3 = b1 & b0;
+            const uint32_t h0 = nb3 & ~b2, h1 = nb3 & b2;
+            Y[0] = h0 & t0; Y[1] = h0 & t1; Y[2] = h0 & t2; Y[3] = h0 & t3;
+            Y[4] = h1 & t0; Y[5] = h1 & t1; Y[6] = h1 & t2; Y[7] = h1 & t3;
+            Y[8] = b3;
+        }
+        const uint32_t famA = s.z & ~X;  // s -> 0:   dE = J y - Delta
+        const uint32_t famB = ~s.z;      // 0 -> s':  dE = -J y + Delta
+        const uint32_t famC = s.z & X;   // s -> -s:  dE = 2 J y
         // general Delta: for each y one of {s -> 0, 0 -> s'} can have dE > 0
         // (sel_a picks it); s -> -s has dE > 0 for y > 0
 #pragma unroll
         for (int q = 0; q < NG; ++q)
             mask[q] = q < 9 ? ((((gt.sel_a_bits >> q) & 1u) ? famA : famB) & Y[q]) : (famC & Y[q - 4]);
     } else {
-        // Delta = 0: dE = J y (s -> 0), -J y (0 -> s'), 2 J y (s -> -s); v = y + 4
-        mask[0] = (famA & Y[5]) | (famB & Y[3]);                 // dE = J
-        mask[1] = (famA & Y[6]) | (famB & Y[2]) | (famC & Y[5]);  // 2J
-        mask[2] = (famA & Y[7]) | (famB & Y[1]);                 // 3J
-        mask[3] = (famA & Y[8]) | (famB & Y[0]) | (famC & Y[6]);  // 4J
-        mask[4] = famC & Y[7];                                   // 6J
-        mask[5] = famC & Y[8];                                   // 8J
+        // Delta = 0.  With the sign carried by y taken as that of s when
+        // s != 0 and as the opposite of the proposed s' when s = 0, every move
+        // has dE = J y (s -> 0 and 0 -> s') or 2 J y (s -> -s): only
+        // y = 1..4 (v = y + 4 = 5..8) falls in a group, and the two families
+        // with dE = J y share their masks.
+        const uint32_t neg = (s.z & s.s) | (~s.z & ~X);
+        uint32_t bits[8];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const uint32_t anti = nbr[n].s ^ neg;
+            bits[n] = nbr[n].z & ~anti;        // neighbour contributes +1 to y
+            bits[4 + n] = ~(nbr[n].z & anti);  // neighbour does not contribute -1
+        }
+        uint32_t b0, b1, b2, b3;
+        count8(bits, b0, b1, b2, b3);  // v in [0, 8]
+        const uint32_t h1 = b2 & ~b3;  // v in 4..7
+        const uint32_t Y5 = h1 & ~b1 & b0, Y6 = h1 & b1 & ~b0, Y7 = h1 & b1 & b0, Y8 = b3;
+        const uint32_t famC = s.z & X;  // s -> -s (the rest: dE = J y)
+        mask[0] = ~famC & Y5;                   // dE = J
+        mask[1] = (famC & Y5) | (~famC & Y6);   // 2J
+        mask[2] = ~famC & Y7;                   // 3J
+        mask[3] = (famC & Y6) | (~famC & Y8);   // 4J
+        mask[4] = famC & Y7;                    // 6J
+        mask[5] = famC & Y8;                    // 8J
     }
     never = 0;
 #pragma unroll
