@@ -38,18 +38,18 @@ SWEEP_SOURCES = ["paper_2503_14688_amd/csrc/kernels.hip", "paper_2503_14688_amd/
                  "paper_2503_14688_amd/csrc/device.hpp", "paper_2503_14688_amd/csrc/kernels.hpp"]
 MEASURED_TRAFFIC = {
     # (workload, sweep strategy): bytes per launch
-    ("ising_L1048576_tc", 2): 221.68e9,
-    ("bc_L262144_t16937", 0): 28.50e9,
-    ("bc_L262144_t16937", 1): 26.88e9,
+    ("ising_L1048576_tc", 2): 224.35e9,
+    ("bc_L262144_t16937", 0): 28.54e9,
+    ("bc_L262144_t16937", 1): 26.87e9,
 }
-MEASURED_WITH = "e7f3277c3fa33ba3"
+MEASURED_WITH = "79efc03bc23169fe"
 # (workload, sweep strategy): wave instructions per 64 words of a colour plane
 # (SQ_INSTS_VALU, SQ_INSTS_SALU) and the clock (GHz, GRBM_GUI_ACTIVE over the
 # dispatch) from the same counter pass
 MEASURED_ISSUE = {
-    ("ising_L1048576_tc", 2): (138.3, 93.0, 2.14),
-    ("bc_L262144_t16937", 0): (292.4, 159.3, 2.16),
-    ("bc_L262144_t16937", 1): (280.3, 139.1, 2.11),
+    ("ising_L1048576_tc", 2): (133.9, 68.0, 2.05),
+    ("bc_L262144_t16937", 0): (283.4, 159.3, 2.14),
+    ("bc_L262144_t16937", 1): (274.3, 139.1, 2.11),
 }
 
 
