@@ -504,6 +504,50 @@ __device__ __forceinline__ void apply_block_2g_pm(const Block4 &r, const PlaneMa
     }
 }
 
+// apply_block_2g for block 0 or 1 (planes 0..7) with a wave-uniform branch
+// per plane on its two threshold bits (pg: GroupTable::plane_groups word of
+// the block, byte q = plane 4 BLK + q, bit 0 group 0, bit 1 group 1).  H =
+// the group-1 (dE = 8J) sites, the other undecided sites are group 0.  Each
+// case is two vector operations (one when neither bit is set):
+//   neither: none accepted, und &= ~u
+//   group 0: accepted und & ~H & ~u, still tied und & (u ^ H)
+//   group 1: accepted und & H & ~u, still tied und & ~(u ^ H)
+//   both:    accepted und & ~u, still tied und & u
+// The operations are volatile so that no case is evaluated outside its
+// branch.
+template <int BLK>
+__device__ __forceinline__ void apply_block_2g_sw(const Block4 &r, uint32_t pg, uint32_t H, uint32_t &undecided,
+                                                  uint32_t &accepted)
+{
+    uint32_t n[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t u = r.v[q];
+        uint32_t und = undecided, nw, nu;
+        switch ((pg >> (8 * q)) & 3u) {
+        case 0u:
+            nw = 0u;
+            asm volatile("v_bitop3_b32 %0, %1, %2, %2 bitop3:0x10" : "=v"(nu) : "v"(und), "v"(u));
+            break;
+        case 1u:
+            asm volatile("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x10" : "=v"(nw) : "v"(und), "v"(H), "v"(u));
+            asm volatile("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x60" : "=v"(nu) : "v"(und), "v"(H), "v"(u));
+            break;
+        case 2u:
+            asm volatile("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x40" : "=v"(nw) : "v"(und), "v"(H), "v"(u));
+            asm volatile("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x90" : "=v"(nu) : "v"(und), "v"(H), "v"(u));
+            break;
+        default:
+            asm volatile("v_bitop3_b32 %0, %1, %2, %2 bitop3:0x10" : "=v"(nw) : "v"(und), "v"(u));
+            asm volatile("v_bitop3_b32 %0, %1, %2, %2 bitop3:0x80" : "=v"(nu) : "v"(und), "v"(u));
+            break;
+        }
+        n[q] = nw;
+        undecided = nu;
+    }
+    accepted |= (n[0] | n[1]) | (n[2] | n[3]);
+}
+
 // Full adder and half adder on bit-sliced operands.
 __device__ __forceinline__ void full_add(uint32_t a, uint32_t b, uint32_t c, uint32_t &s, uint32_t &carry)
 {

@@ -139,6 +139,7 @@ GroupTable make_groups(int model, uint32_t bc_groups, double J, double Delta, do
         set_group(gt, 0, r, thr);
         r = metropolis_rule(delta_energy(J, Delta, 1, -1, 4), T, &thr);
         set_group(gt, 1, r, thr);
+        fill_plane_groups(gt);
         return gt;
     }
     for (int v = 0; v < 9; ++v) {

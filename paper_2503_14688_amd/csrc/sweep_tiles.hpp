@@ -127,7 +127,9 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
     const uint32_t *oth = lat.planes + (c ? 0 : lat.plane_u32);
     const uint64_t nitems = (uint64_t)(L / R) * W;
     const uint32_t thr[2] = {gt.thr[0], gt.thr[1]};
-    const PlaneMasks2 pm = plane_masks_2g(thr);
+    PlaneMasks2 pm;
+    if constexpr (!UNIFORM)
+        pm = plane_masks_2g(thr);
     const bool rng3 = gt.rng_bits & 1u, rng4 = gt.rng_bits & 2u;
     const bool nev3 = gt.never_bits & 1u, nev4 = gt.never_bits & 2u;
     const uint32_t k0 = lat.key0, k1 = lat.key1;
@@ -200,9 +202,18 @@ __device__ __forceinline__ void ising_tile_compact(const Lattice &lat, uint32_t 
             // blocks 0 and 1 for every word: the wavefront would run them
             // anyway unless all 64 of its words were settled, which is rare
             const Block4 b0 = philox_block<UNIFORM>(i, w, t, stream_tag(kPurposeAccept, c, 0), k0, k1);
-            apply_block_2g_pm<0>(b0, pm, need[1], und, acc);
+            // row-uniform tiles (the large lattices): one branch per plane on
+            // its two threshold bits; otherwise the prepared masks (measured
+            // faster there, in the batched kernel)
+            if constexpr (UNIFORM)
+                apply_block_2g_sw<0>(b0, gt.plane_groups[0], need[1], und, acc);
+            else
+                apply_block_2g_pm<0>(b0, pm, need[1], und, acc);
             const Block4 b1 = philox_block<UNIFORM>(i, w, t, stream_tag(kPurposeAccept, c, 1), k0, k1);
-            apply_block_2g_pm<1>(b1, pm, need[1], und, acc);
+            if constexpr (UNIFORM)
+                apply_block_2g_sw<1>(b1, gt.plane_groups[1], need[1], und, acc);
+            else
+                apply_block_2g_pm<1>(b1, pm, need[1], und, acc);
             und = valid ? und : 0u;
         }
         const unsigned long long bal = __ballot(und != 0u);
