@@ -410,7 +410,9 @@ __device__ __forceinline__ void apply_block_any(const Block4 &r, uint32_t blk, c
         apply_block<NG>(r, blk, need, thr, undecided, accepted);
 }
 
-template <int NG>
+// ROW_UNIFORM: the row is the same across the wavefront (the row-uniform
+// Philox form; used by the six-group test).
+template <int NG, bool ROW_UNIFORM = false>
 __device__ __forceinline__ uint32_t metropolis_accept(const uint32_t (&need)[NG], const uint32_t (&thr)[NG],
                                                       uint32_t always, uint32_t row, uint32_t word,
                                                       uint32_t t, uint32_t colour, uint32_t k0, uint32_t k1,
@@ -423,8 +425,13 @@ __device__ __forceinline__ uint32_t metropolis_accept(const uint32_t (&need)[NG]
     uint32_t accepted = always;
     for (uint32_t blk = 0; blk < 8u && undecided != 0u; ++blk) {
         const uint32_t tag = stream_tag(kPurposeAccept, colour, blk);
-        const Block4 r = NG == 2 ? philox4x32_10_vec(row, word, t, tag, k0, k1)
-                                 : philox4x32_10(row, word, t, tag, k0, k1);
+        Block4 r;
+        if constexpr (ROW_UNIFORM)
+            r = philox4x32_10_ru(row, word, t, tag, k0, k1);
+        else if constexpr (NG == 2)
+            r = philox4x32_10_vec(row, word, t, tag, k0, k1);
+        else
+            r = philox4x32_10(row, word, t, tag, k0, k1);
         apply_block_any<NG>(r, blk, need, thr, pats, undecided, accepted);
     }
     return accepted;

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_ising(Lattice lat, uint32_t c,
 // One kernel per group count and classification form, so that each keeps
 // only its own thresholds and masks in registers (one kernel with both group
 // counts spills scalar registers in the loops of either).
-template <bool MEASURE, int V, int NG, bool PLAIN>
+template <bool MEASURE, int V, int NG, bool PLAIN, bool UNIFORM = false>
 __global__ __launch_bounds__(kBlock) void k_sweep_bc(Lattice lat, uint32_t c, uint32_t t, GroupTable gt,
                                                      unsigned long long *acc)
 {
@@ -109,10 +109,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep_bc(Lattice lat, uint32_t c, ui
         using QB = BcList<NG, bc_list_cap(V), R>;
         __shared__ QB Q[kWaves];
         for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-            bc_tile_compact<MEASURE, R, NG, QB, PLAIN>(lat, c, t, gt, gt.plane_groups, tile, Q[threadIdx.x >> 6], e);
+            bc_tile_compact<MEASURE, R, NG, QB, PLAIN, UNIFORM>(lat, c, t, gt, gt.plane_groups, tile,
+                                                                Q[threadIdx.x >> 6], e);
     } else {
         for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-            bc_tile<MEASURE, R, NG, PLAIN>(lat, c, t, gt, gt.plane_groups, tile, e);
+            bc_tile<MEASURE, R, NG, PLAIN, UNIFORM>(lat, c, t, gt, gt.plane_groups, tile, e);
     }
     if (MEASURE)
         block_reduce_atomic<kEmCounters>(e, acc);
@@ -325,7 +326,10 @@ hipError_t launch_half_sweep_v(const Lattice &lat, uint32_t colour, uint32_t t, 
     } else {
         static const unsigned g = 65536u;
         const dim3 grid(g < tiles ? g : (unsigned)tiles);
-        if (lat.bc_groups == kBcGroupsDelta0 && bc_plain<kBcGroupsDelta0>(gt))
+        if (lat.bc_groups == kBcGroupsDelta0 && bc_plain<kBcGroupsDelta0>(gt) && lat.W % 64 == 0)
+            hipLaunchKernelGGL((k_sweep_bc<M, V, kBcGroupsDelta0, true, true>), grid, block, 0, st, lat, colour, t,
+                               gt, em_acc);
+        else if (lat.bc_groups == kBcGroupsDelta0 && bc_plain<kBcGroupsDelta0>(gt))
             hipLaunchKernelGGL((k_sweep_bc<M, V, kBcGroupsDelta0, true>), grid, block, 0, st, lat, colour, t, gt, em_acc);
         else if (lat.bc_groups == kBcGroupsDelta0)
             hipLaunchKernelGGL((k_sweep_bc<M, V, kBcGroupsDelta0, false>), grid, block, 0, st, lat, colour, t, gt,

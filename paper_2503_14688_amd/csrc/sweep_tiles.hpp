@@ -501,7 +501,10 @@ __device__ __forceinline__ void bc_nbrs(const uint32_t *oth, uint32_t L, uint32_
 // next row's words before it draws random planes.
 // pats: the table's plane_groups, read with uniform loads (the kernel
 // argument's, or the batch table's in global memory).
-template <bool MEASURE, int R, int NG, bool PLAIN = false>
+// UNIFORM: W is a multiple of 64, so a wavefront's 64 items share one row
+// group (and fill whole tiles): the row is wave-uniform and the Philox rounds
+// start in scalar registers, as in ising_tile_lazy.
+template <bool MEASURE, int R, int NG, bool PLAIN = false, bool UNIFORM = false>
 __device__ __forceinline__ void bc_tile(const Lattice &lat, uint32_t c, uint32_t t, const GroupTable &gt,
                                         const uint32_t *pats, uint64_t tile, unsigned long long (&e)[kEmCounters])
 {
@@ -510,13 +513,19 @@ __device__ __forceinline__ void bc_tile(const Lattice &lat, uint32_t c, uint32_t
     const uint32_t *oth = lat.planes + (c ? 0 : lat.plane_u32);
     const uint64_t nitems = (uint64_t)(L / R) * W;
     const uint64_t g = tile * kBlock + threadIdx.x;
-    if (g >= nitems)
+    if (!UNIFORM && g >= nitems)
         return;
     uint32_t thr[NG];
 #pragma unroll
     for (int q = 0; q < NG; ++q)
         thr[q] = gt.thr[q];
-    const uint32_t rg = row_group(g, W, nitems);
+    uint32_t rg;
+    if (UNIFORM) {
+        const uint32_t wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) & ~63u;
+        rg = __builtin_amdgcn_readfirstlane((uint32_t)((tile * kBlock + wave0) / W));
+    } else {
+        rg = row_group(g, W, nitems);
+    }
     const uint32_t w = (uint32_t)(g - (uint64_t)rg * W);
     const uint32_t i0 = rg * R;
     const uint32_t wl = (w == 0 ? W : w) - 1u;
@@ -539,14 +548,16 @@ __device__ __forceinline__ void bc_tile(const Lattice &lat, uint32_t c, uint32_t
         const uint32_t odd = (i + c) & 1u;
         const Pair side{side_word(cur.z, nbw.z, odd), side_word(cur.s, nbw.s, odd)};
         const Pair nbr[4] = {up, dn, cur, side};
-        const uint32_t X = philox4x32_10(i, w, t, stream_tag(kPurposePropose, c, 0), lat.key0, lat.key1).v[0];
+        const uint32_t X =
+            philox_block<UNIFORM>(i, w, t, stream_tag(kPurposePropose, c, 0), lat.key0, lat.key1).v[0];
         uint32_t need[NG], never;
         bc_classify<NG, PLAIN>(gt, s, nbr, X, need, never);
         uint32_t any = 0;
 #pragma unroll
         for (int q = 0; q < NG; ++q)
             any |= need[q];
-        const uint32_t F = metropolis_accept<NG>(need, thr, ~(any | never), i, w, t, c, lat.key0, lat.key1, pats);
+        const uint32_t F =
+            metropolis_accept<NG, UNIFORM>(need, thr, ~(any | never), i, w, t, c, lat.key0, lat.key1, pats);
         const Pair n = bc_new_state(F, s, X);
         bc_store(own, (size_t)i * W + w, n);
         if (MEASURE)
@@ -575,7 +586,7 @@ struct BcList {
     uint2 stage[R][64];
 };
 
-template <bool MEASURE, int R, int NG, typename List, bool PLAIN = false>
+template <bool MEASURE, int R, int NG, typename List, bool PLAIN = false, bool UNIFORM = false>
 __device__ __forceinline__ void bc_tile_compact(const Lattice &lat, uint32_t c, uint32_t t, const GroupTable &gt,
                                                 const uint32_t *pats, uint64_t tile, List &Q,
                                                 unsigned long long (&e)[kEmCounters])
@@ -592,9 +603,16 @@ __device__ __forceinline__ void bc_tile_compact(const Lattice &lat, uint32_t c, 
     const uint32_t k0 = lat.key0, k1 = lat.key1;
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t g = tile * kBlock + threadIdx.x;
-    const bool valid = g < nitems;
-    const uint32_t rg = valid ? row_group(g, W, nitems) : 0u;
-    const uint32_t w = valid ? (uint32_t)(g - (uint64_t)rg * W) : 0u;
+    const bool valid = UNIFORM || g < nitems;  // UNIFORM: whole tiles (see bc_tile)
+    uint32_t rg, w;
+    if (UNIFORM) {
+        const uint32_t wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) & ~63u;
+        rg = __builtin_amdgcn_readfirstlane((uint32_t)((tile * kBlock + wave0) / W));
+        w = (uint32_t)(g - (uint64_t)rg * W);
+    } else {
+        rg = valid ? row_group(g, W, nitems) : 0u;
+        w = valid ? (uint32_t)(g - (uint64_t)rg * W) : 0u;
+    }
     const uint32_t i0 = rg * R;
     Q.i0[lane] = i0;
     Q.w[lane] = w;
@@ -625,7 +643,7 @@ __device__ __forceinline__ void bc_tile_compact(const Lattice &lat, uint32_t c, 
         for (int q = 0; q < NG; ++q)
             need[q] = 0;
         if (valid) {
-            X = philox4x32_10(i, w, t, stream_tag(kPurposePropose, c, 0), k0, k1).v[0];
+            X = philox_block<UNIFORM>(i, w, t, stream_tag(kPurposePropose, c, 0), k0, k1).v[0];
             uint32_t never;
             bc_classify<NG, PLAIN>(gt, s, nbr, X, need, never);
 #pragma unroll
@@ -633,11 +651,11 @@ __device__ __forceinline__ void bc_tile_compact(const Lattice &lat, uint32_t c, 
                 und |= need[q];
             acc = ~(und | never);
             if (und != 0u) {
-                const Block4 b = philox4x32_10(i, w, t, stream_tag(kPurposeAccept, c, 0), k0, k1);
+                const Block4 b = philox_block<UNIFORM>(i, w, t, stream_tag(kPurposeAccept, c, 0), k0, k1);
                 apply_block_any<NG>(b, 0u, need, thr, pats, und, acc);
             }
             if (und != 0u) {
-                const Block4 b = philox4x32_10(i, w, t, stream_tag(kPurposeAccept, c, 1), k0, k1);
+                const Block4 b = philox_block<UNIFORM>(i, w, t, stream_tag(kPurposeAccept, c, 1), k0, k1);
                 apply_block_any<NG>(b, 1u, need, thr, pats, und, acc);
             }
         }

@@ -275,6 +275,27 @@ def test_uniform_row_tiles_all_strategies(gpu):
         lat.close()
 
 
+def test_blume_capel_uniform_row_tiles_all_strategies(gpu):
+    """Blume-Capel L = 4096 at Delta = 0: a plane row is 64 words, so every
+    strategy takes the row-uniform form of its tile (Philox rounds started in
+    scalar registers) with the select-free classification; each reproduces
+    the oracle's trajectory and bond sum, with the E/M sums fused into the
+    last sweep."""
+    L, seed = 4096, 4242
+    T = np.full(6, workloads.TC_BC)
+    s = oracle.init(1, L, seed)
+    oracle.sweep(1, s, seed, 1.0, 0.0, 0, T)
+    bond = oracle.measure(s, [])["bond"]
+    for v in range(5):
+        print(f"strategy {v}", flush=True)
+        lat = make(gpu, 1, L, seed)
+        lat.variant = v
+        lat.sweep(T, fuse_measure=True)
+        assert lat.measure()["bond"] == bond, v
+        assert np.array_equal(lat.spins(), s), v
+        lat.close()
+
+
 def test_ising_L4096_check_run(gpu):
     """The bit-exact check lattice of the large Ising workload: 2^12 x 2^12, 64 sweeps."""
     w = workloads.ISING_CHECK
