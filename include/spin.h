@@ -248,7 +248,8 @@ int spin_measure_fourier(spin_handle *h, spin_fourier *out, int64_t *row_sums, i
  * the quench of protocol 1 and the time-dependent bath of protocol 2),
  * advanced together.  Every replica evolves exactly as it would alone
  * through spin_sweep with the same T array.  One launch per half-sweep
- * covers all replicas; a run of n sweeps is captured as one HIP graph.
+ * covers all replicas; runs of 2^k sweeps (k <= 8) are captured once as HIP
+ * graphs, and a run of any length replays them.
  * ------------------------------------------------------------------------ */
 
 typedef struct spin_batch spin_batch;

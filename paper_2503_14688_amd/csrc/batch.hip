@@ -1,11 +1,11 @@
 // Batched replicas (C ABI spin_batch_*): many independent lattices of mixed
 // size and model, each following its own bath-temperature schedule (paper,
 // Thermal protocols), advanced together by one launch per half-sweep over a
-// flat list of all replicas' tiles.  A run of n sweeps is captured once as a
-// HIP graph of 2n launches (plus one that advances the device step counter)
-// and replayed for every later run of n sweeps; the sweep strategy (rows per thread,
-// per-word or compacting lazy test) is chosen by timing every strategy on
-// scratch copies of the lattices.
+// flat list of all replicas' tiles.  Runs of 2^k sweeps (k <= 8) are
+// captured once each as HIP graphs of 2^(k+1) launches (plus one that
+// advances the device step counter), and a run of any length replays them;
+// the sweep strategy (rows per thread, per-word or compacting lazy test) is
+// chosen by timing every strategy on scratch copies of the lattices.
 #include "batch_kernels.hpp"
 #include "host.hpp"
 
@@ -23,6 +23,10 @@ using namespace spin_host;
 // Tile layouts: rows per thread of the Ising tiles (4 or 8) x of the
 // Blume-Capel tiles.
 constexpr int kLayouts = 4;
+// Runs are replayed from captured runs of 2^k sweeps, k <= kGraphLog: a run
+// of n sweeps is n / 256 replays of the 256-sweep graph and one replay per
+// set bit of n % 256.
+constexpr int kGraphLog = 8;
 
 struct spin_batch {
     std::vector<spin_handle *> reps;
@@ -41,10 +45,14 @@ struct spin_batch {
     GroupTable *d_tables = nullptr;
     unsigned long long *d_meas = nullptr;  // measurement counters of every replica
     size_t meas_cap = 0;                   // entries
+    spin::MeasItem *d_items = nullptr;     // per replica: lattice and counter block
+    uint32_t *d_ids = nullptr;             // replica lists of the batched measurement launches
+    std::vector<spin::MeasItem> h_items;   // host sides of the two (kept until the copy is done)
+    std::vector<uint32_t> h_ids;
     uint32_t *d_step = nullptr;          // schedule step on the device (= t between runs)
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    uint32_t graph_n = 0;                // run length and strategy the graph was captured for
+    // captured runs of 2^k sweeps, k = 0 .. kGraphLog, for strategy graph_variant
+    hipGraph_t graph[kGraphLog + 1] = {};
+    hipGraphExec_t exec[kGraphLog + 1] = {};
     int graph_variant = -1;
 };
 
@@ -58,16 +66,26 @@ int layout_of(int bv)
            (spin::variant_rows(spin::batch_bc_variant(bv)) == 8 ? 2 : 0);
 }
 
+void drop_graphs(spin_batch *b)
+{
+    for (int k = 0; k <= kGraphLog; ++k) {
+        if (b->exec[k])
+            (void)hipGraphExecDestroy(b->exec[k]);
+        if (b->graph[k])
+            (void)hipGraphDestroy(b->graph[k]);
+        b->exec[k] = nullptr;
+        b->graph[k] = nullptr;
+    }
+    b->graph_variant = -1;
+}
+
 void release(spin_batch *b)
 {
     if (!b)
         return;
     if (b->stream)
         (void)hipStreamSynchronize(b->stream);
-    if (b->exec)
-        (void)hipGraphExecDestroy(b->exec);
-    if (b->graph)
-        (void)hipGraphDestroy(b->graph);
+    drop_graphs(b);
     for (int k = 0; k < kLayouts; ++k) {
         if (b->d_reps[k])
             (void)hipFree(b->d_reps[k]);
@@ -78,6 +96,10 @@ void release(spin_batch *b)
         (void)hipFree(b->d_tables);
     if (b->d_meas)
         (void)hipFree(b->d_meas);
+    if (b->d_items)
+        (void)hipFree(b->d_items);
+    if (b->d_ids)
+        (void)hipFree(b->d_ids);
     if (b->d_step)
         (void)hipFree(b->d_step);
     for (spin_handle *h : b->reps)
@@ -392,38 +414,42 @@ int spin_batch_run(spin_batch *b, uint32_t n, uint32_t flags)
     if (flags & SPIN_BATCH_DIRECT) {
         if (int rc = launch_sweeps(b, b->variant, n, true, b->stream))
             return rc;
-    } else if (b->exec && b->graph_n == n && b->graph_variant == b->variant) {
-        // the same run length again: the captured launches read their steps
-        // from the device counter, so the graph replays as it is
-        HIP_TRY(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
     } else {
-        HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
-        if (b->exec) {
-            (void)hipGraphExecDestroy(b->exec);
-            b->exec = nullptr;
+        if (b->graph_variant != b->variant) {
+            HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+            drop_graphs(b);
+            b->graph_variant = b->variant;
         }
-        if (b->graph) {
-            (void)hipGraphDestroy(b->graph);
-            b->graph = nullptr;
+        // The captured launches read their schedule steps from the device
+        // counter and advance it at the end, so the graphs of a run's pieces
+        // replay one after another as they are.
+        for (uint32_t left = n; left > 0;) {
+            int k = kGraphLog;
+            while ((1u << k) > left)
+                --k;
+            if (!b->exec[k]) {
+                HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+                HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+                int rc = launch_sweeps(b, b->variant, 1u << k, true, b->stream);
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamEndCapture(b->stream, &g);
+                if (rc) {
+                    if (g)
+                        (void)hipGraphDestroy(g);
+                    return rc;
+                }
+                if (e != hipSuccess)
+                    return hip_fail(e, "hipStreamEndCapture");
+                b->graph[k] = g;
+                e = hipGraphInstantiate(&b->exec[k], g, nullptr, nullptr, 0);
+                if (e != hipSuccess) {
+                    b->exec[k] = nullptr;
+                    return hip_fail(e, "hipGraphInstantiate");
+                }
+            }
+            HIP_TRY(hipGraphLaunch(b->exec[k], b->stream), "hipGraphLaunch");
+            left -= 1u << k;
         }
-        b->graph_n = 0;
-        b->graph_variant = -1;
-        HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-        int rc = launch_sweeps(b, b->variant, n, true, b->stream);
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(b->stream, &g);
-        if (rc) {
-            if (g)
-                (void)hipGraphDestroy(g);
-            return rc;
-        }
-        if (e != hipSuccess)
-            return hip_fail(e, "hipStreamEndCapture");
-        b->graph = g;
-        HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
-        b->graph_n = n;
-        b->graph_variant = b->variant;
-        HIP_TRY(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
     }
     b->t += n;
     for (size_t r = 0; r < b->reps.size(); ++r) {
@@ -462,9 +488,9 @@ int spin_batch_measure(spin_batch *b, const uint32_t *r, uint32_t n_r, spin_meas
             if (r[q] == 0 || r[q] >= L)
                 return fail(-EINVAL, "separation %u outside 0 < r < L = %u of replica %zu", r[q], L, k);
     }
-    // every replica's counters in one buffer: one fill, the reduction and
-    // correlation kernels of each replica queued back to back, one copy, one
-    // synchronisation
+    // every replica's counters in one buffer: one fill, then one launch per
+    // kernel and model (or kernel kind) for all replicas at once, one copy,
+    // one synchronisation
     const size_t per = measure_counters(n_r), total = per * b->reps.size();
     if (total > b->meas_cap) {
         HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
@@ -479,14 +505,88 @@ int spin_batch_measure(spin_batch *b, const uint32_t *r, uint32_t n_r, spin_meas
         }
         b->meas_cap = total;
     }
-    HIP_TRY(spin::launch_fill_u64(b->d_meas, total, 0ull, b->stream), "fill kernel launch");
-    for (size_t k = 0; k < b->reps.size(); ++k) {
-        unsigned long long *acc = b->d_meas + k * per;
-        HIP_TRY(spin::launch_measure_em(b->reps[k]->lat, acc, b->stream), "measure kernel launch");
-        if (n_r > 0)
-            if (int rc = queue_correlations(b->reps[k]->lat, r, n_r, acc, b->stream))
-                return rc;
+    const size_t n = b->reps.size();
+    if (n > 65535)
+        return fail(-EINVAL, "%zu replicas: at most 65535 per batched measurement", n);
+    if (!b->d_items) {
+        hipError_t e = hipMalloc(&b->d_items, n * sizeof(spin::MeasItem));
+        if (e == hipSuccess)
+            e = hipMalloc(&b->d_ids, 3 * n * sizeof(uint32_t));
+        if (e != hipSuccess) {
+            if (b->d_items)
+                (void)hipFree(b->d_items);
+            b->d_items = nullptr;
+            b->d_ids = nullptr;
+            return fail(-ENOMEM, "measurement descriptors: %s", hipGetErrorString(e));
+        }
     }
+    // Launch lists: E/M by model (0, 1); horizontal correlations by kernel
+    // kind (2..5) and vertical by kind (6, 7) when r is a prefix of the
+    // sparse set; replicas whose vertical kind does not apply take the
+    // general correlation kernels one by one.
+    constexpr int kLists = 8;
+    std::vector<uint32_t> list[kLists], single;
+    uint32_t blocks[kLists] = {};
+    const bool sparse = n_r > 0 && spin::sparse_prefix(r, (int)n_r);
+    b->h_items.resize(n);
+    for (size_t k = 0; k < n; ++k) {
+        const spin::Lattice &lat = b->reps[k]->lat;
+        b->h_items[k] = spin::MeasItem{lat, b->d_meas + k * per};
+        auto add = [&](int l, uint32_t blk) {
+            list[l].push_back((uint32_t)k);
+            blocks[l] = std::max(blocks[l], blk);
+        };
+        add(lat.model == spin::kIsing ? 0 : 1, spin::measure_em_blocks(lat));
+        if (n_r == 0)
+            continue;
+        const int ky = sparse ? spin::corr_sparse_kind(lat, true) : -1;
+        if (ky < 0) {
+            single.push_back((uint32_t)k);
+            continue;
+        }
+        add(2 + spin::corr_sparse_kind(lat, false), spin::corr_sparse_blocks(lat, false));
+        add(6 + ky, spin::corr_sparse_blocks(lat, true));
+    }
+    b->h_ids.clear();
+    uint32_t first[kLists];
+    for (int l = 0; l < kLists; ++l) {
+        first[l] = (uint32_t)b->h_ids.size();
+        b->h_ids.insert(b->h_ids.end(), list[l].begin(), list[l].end());
+        // E/M and horizontal kernels: about 8192 blocks over all replicas
+        // (32 per CU), each walking more units than in the single-lattice
+        // grid (at most 16 times as many, which keeps the horizontal
+        // kernel's 32-bit lane counters far from overflow); fewer blocks
+        // also mean fewer counter atomics at the end of each block.
+        if (l < 6 && !list[l].empty()) {
+            const uint32_t cnt = (uint32_t)list[l].size();
+            const uint32_t want = std::max((8192u + cnt - 1) / cnt, (blocks[l] + 15u) / 16u);
+            blocks[l] = std::min(blocks[l], want);
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(b->d_items, b->h_items.data(), n * sizeof(spin::MeasItem), hipMemcpyHostToDevice,
+                           b->stream),
+            "hipMemcpyAsync");
+    if (!b->h_ids.empty())
+        HIP_TRY(hipMemcpyAsync(b->d_ids, b->h_ids.data(), b->h_ids.size() * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, b->stream),
+                "hipMemcpyAsync");
+    HIP_TRY(spin::launch_fill_u64(b->d_meas, total, 0ull, b->stream), "fill kernel launch");
+    for (int l = 0; l < kLists; ++l) {
+        const uint32_t cnt = (uint32_t)list[l].size();
+        const uint32_t *ids = b->d_ids + first[l];
+        if (l < 2)
+            HIP_TRY(spin::launch_measure_em_batch(l, b->d_items, ids, cnt, blocks[l], b->stream),
+                    "batched measure kernel launch");
+        else if (l < 6)
+            HIP_TRY(spin::launch_corr_sparse_batch(l - 2, false, b->d_items, ids, cnt, blocks[l], (int)n_r, b->stream),
+                    "batched correlation kernel launch");
+        else
+            HIP_TRY(spin::launch_corr_sparse_batch(l - 6, true, b->d_items, ids, cnt, blocks[l], (int)n_r, b->stream),
+                    "batched correlation kernel launch");
+    }
+    for (uint32_t k : single)
+        if (int rc = queue_correlations(b->reps[k]->lat, r, n_r, b->d_meas + k * per, b->stream))
+            return rc;
     std::vector<unsigned long long> acc(total);
     HIP_TRY(hipMemcpyAsync(acc.data(), b->d_meas, total * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                            b->stream),

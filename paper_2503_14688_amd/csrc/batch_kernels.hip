@@ -28,20 +28,6 @@ union BatchList {
 // flat tile list maps each global tile to (replica, local tile); replica r's
 // thresholds for this sweep are tables[sched(r) * stride + step] and its
 // random stream runs at sweep index t0(r) + step.
-// A copy of *p in scalar registers (p is the same for the whole wavefront).
-template <typename T>
-__device__ __forceinline__ T wave_uniform_copy(const T *p)
-{
-    static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
-    T out;
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(p);
-    uint32_t *dst = reinterpret_cast<uint32_t *>(&out);
-#pragma unroll
-    for (int k = 0; k < (int)(sizeof(T) / 4); ++k)
-        dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
-    return out;
-}
-
 template <int BV, int MODELS>
 __global__ __launch_bounds__(kBlock) void k_batch_half_sweep(const BatchReplica *__restrict__ reps,
                                                              const uint32_t *__restrict__ tile_rep, uint64_t ntiles,

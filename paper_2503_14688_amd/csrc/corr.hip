@@ -261,7 +261,7 @@ __device__ __forceinline__ void flush_groups(const uint32_t (&ca)[PER], const ui
 }
 
 template <int MODEL>
-__global__ __launch_bounds__(kBlock) void k_corr_x_sparse(Lattice lat, int n_r, unsigned long long *acc)
+__device__ __forceinline__ void corr_x_sparse(const Lattice &lat, int n_r, unsigned long long *acc)
 {
     __shared__ XTile<MODEL> t;
     constexpr int E = XTile<MODEL>::E;
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_corr_x_sparse(Lattice lat, int n_r, 
 }
 
 template <int MODEL>
-__global__ __launch_bounds__(kBlock) void k_corr_x_runs(Lattice lat, int n_r, unsigned long long *acc)
+__device__ __forceinline__ void corr_x_runs(const Lattice &lat, int n_r, unsigned long long *acc)
 {
     __shared__ XRunTile<MODEL> t;
     constexpr int E = XRunTile<MODEL>::E;
@@ -341,6 +341,31 @@ __global__ __launch_bounds__(kBlock) void k_corr_x_runs(Lattice lat, int n_r, un
         }
     }
     flush_groups<MODEL != kIsing, kXPer>(ca, cb, sg, n_r, acc);
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(kBlock) void k_corr_x_sparse(Lattice lat, int n_r, unsigned long long *acc)
+{
+    corr_x_sparse<MODEL>(lat, n_r, acc);
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(kBlock) void k_corr_x_runs(Lattice lat, int n_r, unsigned long long *acc)
+{
+    corr_x_runs<MODEL>(lat, n_r, acc);
+}
+
+// Lattice ids[blockIdx.y] of a batch (its horizontal counters follow the
+// E/M counters).
+template <int MODEL, bool RUNS>
+__global__ __launch_bounds__(kBlock) void k_corr_x_batch(const MeasItem *__restrict__ items,
+                                                         const uint32_t *__restrict__ ids, int n_r)
+{
+    const MeasItem it = wave_uniform_copy(items + __builtin_amdgcn_readfirstlane(ids[blockIdx.y]));
+    if (RUNS)
+        corr_x_runs<MODEL>(it.lat, n_r, it.acc + kEmCounters);
+    else
+        corr_x_sparse<MODEL>(it.lat, n_r, it.acc + kEmCounters);
 }
 
 // -------------------------------------------------------------- vertical --
@@ -568,8 +593,7 @@ static uint32_t y_ring_rows(int n_r)
 }
 
 template <int MODEL>
-__global__ __launch_bounds__(kYThreads) void k_corr_y_ring(Lattice lat, int n_r, uint32_t RING,
-                                                           unsigned long long *acc)
+__device__ __forceinline__ void corr_y_ring(const Lattice &lat, int n_r, uint32_t RING, unsigned long long *acc)
 {
     extern __shared__ uint32_t ring[];  // (RING + kChunk) rows of kRingCols words
     const int jr = threadIdx.x % kChunk;  // ring row of the chunk
@@ -588,6 +612,23 @@ __global__ __launch_bounds__(kYThreads) void k_corr_y_ring(Lattice lat, int n_r,
     default: y_walk<MODEL, 3 * kYPer>(lat, n_r, RING, ring, jr, ca, cb); break;
     }
     flush_groups<MODEL != kIsing, kYPer>(ca, cb, sg, n_r, acc);
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(kYThreads) void k_corr_y_ring(Lattice lat, int n_r, uint32_t RING,
+                                                           unsigned long long *acc)
+{
+    corr_y_ring<MODEL>(lat, n_r, RING, acc);
+}
+
+// Lattice ids[blockIdx.y] of a batch (its vertical counters follow the E/M
+// and horizontal counters).
+template <int MODEL>
+__global__ __launch_bounds__(kYThreads) void k_corr_y_batch(const MeasItem *__restrict__ items,
+                                                            const uint32_t *__restrict__ ids, int n_r, uint32_t RING)
+{
+    const MeasItem it = wave_uniform_copy(items + __builtin_amdgcn_readfirstlane(ids[blockIdx.y]));
+    corr_y_ring<MODEL>(it.lat, n_r, RING, it.acc + kEmCounters + 2 * n_r);
 }
 
 } // namespace
@@ -618,6 +659,54 @@ static unsigned corr_grid(uint64_t items, unsigned cap)
 {
     uint64_t g = items < cap ? items : cap;
     return (unsigned)(g ? g : 1);
+}
+
+int corr_sparse_kind(const Lattice &lat, bool vertical)
+{
+    const int m = lat.model == kIsing ? 0 : 1;
+    if (!vertical)
+        return 2 * m + (lat.W % kTileW == 0 ? 1 : 0);
+    const uint32_t sw = m == 0 ? YShape<kIsing>::SW : YShape<kBlumeCapel>::SW;
+    return lat.W % sw == 0 ? m : -1;
+}
+
+uint32_t corr_sparse_blocks(const Lattice &lat, bool vertical)
+{
+    if (!vertical)
+        return corr_grid((uint64_t)lat.L * ((lat.W + kTileW - 1) / kTileW), 2048);
+    return corr_grid(lat.W / (lat.model == kIsing ? YShape<kIsing>::SW : YShape<kBlumeCapel>::SW), 256);
+}
+
+hipError_t launch_corr_sparse_batch(int kind, bool vertical, const MeasItem *items, const uint32_t *ids, uint32_t n,
+                                    uint32_t blocks, int n_r, hipStream_t st)
+{
+    if (n == 0)
+        return hipSuccess;
+    if (n > 65535u || blocks == 0 || n_r <= 0 || n_r > kSparseN || kind < 0 || kind > (vertical ? 1 : 3))
+        return hipErrorInvalidValue;
+    if (!vertical) {
+        const dim3 grid(blocks, n), block(kBlock);
+        switch (kind) {
+        case 0: hipLaunchKernelGGL((k_corr_x_batch<kIsing, false>), grid, block, 0, st, items, ids, n_r); break;
+        case 1: hipLaunchKernelGGL((k_corr_x_batch<kIsing, true>), grid, block, 0, st, items, ids, n_r); break;
+        case 2: hipLaunchKernelGGL((k_corr_x_batch<kBlumeCapel, false>), grid, block, 0, st, items, ids, n_r); break;
+        default: hipLaunchKernelGGL((k_corr_x_batch<kBlumeCapel, true>), grid, block, 0, st, items, ids, n_r); break;
+        }
+        return hipGetLastError();
+    }
+    const uint32_t RING = y_ring_rows(n_r);
+    const size_t lds = (size_t)(RING + kChunk) * kRingCols * sizeof(uint32_t);
+    const dim3 grid(blocks, n), block(kYThreads);
+    if (kind == 0) {
+        (void)hipFuncSetAttribute((const void *)k_corr_y_batch<kIsing>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        hipLaunchKernelGGL(k_corr_y_batch<kIsing>, grid, block, lds, st, items, ids, n_r, RING);
+    } else {
+        (void)hipFuncSetAttribute((const void *)k_corr_y_batch<kBlumeCapel>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_corr_y_batch<kBlumeCapel>, grid, block, lds, st, items, ids, n_r, RING);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_corr_sparse(const Lattice &lat, bool vertical, int n_r, unsigned long long *acc, hipStream_t st)

@@ -607,4 +607,20 @@ __device__ __forceinline__ void block_reduce_atomic(unsigned long long (&v)[N], 
     }
 }
 
+// A copy of *p in scalar registers (p is the same for the whole wavefront):
+// a descriptor that a block reads from memory instead of its kernel
+// arguments, kept where the arguments would be.
+template <typename T>
+__device__ __forceinline__ T wave_uniform_copy(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
+    T out;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(p);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&out);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k)
+        dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+    return out;
+}
+
 } // namespace spin

@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_bc(Lattice lat, uint32_t c, ui
 // ------------------------------------------ energy / magnetisation sums --
 
 template <int MODEL>
-__global__ __launch_bounds__(kBlock) void k_measure_em(Lattice lat, unsigned long long *acc)
+__device__ __forceinline__ void measure_em(const Lattice &lat, unsigned long long *acc)
 {
     // Walks the colour-1 plane: every bond has exactly one colour-1 end, and
     // word (i, w) of plane 0 is counted once as the same-row word.
@@ -164,6 +164,21 @@ __global__ __launch_bounds__(kBlock) void k_measure_em(Lattice lat, unsigned lon
         }
     }
     block_reduce_atomic<kEmCounters>(e, acc);
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(kBlock) void k_measure_em(Lattice lat, unsigned long long *acc)
+{
+    measure_em<MODEL>(lat, acc);
+}
+
+// The same for lattice ids[blockIdx.y] of a batch.
+template <int MODEL>
+__global__ __launch_bounds__(kBlock) void k_measure_em_batch(const MeasItem *__restrict__ items,
+                                                             const uint32_t *__restrict__ ids)
+{
+    const MeasItem it = wave_uniform_copy(items + __builtin_amdgcn_readfirstlane(ids[blockIdx.y]));
+    measure_em<MODEL>(it.lat, it.acc);
 }
 
 // ------------------------------------------------------- correlations --
@@ -362,6 +377,23 @@ hipError_t launch_half_sweep(const Lattice &lat, uint32_t colour, uint32_t t, co
 uint64_t sweep_tiles(const Lattice &lat, int rows)
 {
     return rows == 4 ? tiles_of<4>(lat) : tiles_of<8>(lat);
+}
+
+uint32_t measure_em_blocks(const Lattice &lat) { return grid_for((uint64_t)lat.L * lat.W); }
+
+hipError_t launch_measure_em_batch(int model, const MeasItem *items, const uint32_t *ids, uint32_t n,
+                                   uint32_t blocks, hipStream_t st)
+{
+    if (n == 0)
+        return hipSuccess;
+    if (n > 65535u || blocks == 0)
+        return hipErrorInvalidValue;
+    const dim3 grid(blocks, n), block(kBlock);
+    if (model == kIsing)
+        hipLaunchKernelGGL(k_measure_em_batch<kIsing>, grid, block, 0, st, items, ids);
+    else
+        hipLaunchKernelGGL(k_measure_em_batch<kBlumeCapel>, grid, block, 0, st, items, ids);
+    return hipGetLastError();
 }
 
 hipError_t launch_measure_em(const Lattice &lat, unsigned long long *em_acc, hipStream_t st)

@@ -82,6 +82,27 @@ bool corr_sparse_y_ok(const Lattice &lat, const uint32_t *r, int n_r);
 hipError_t launch_corr_sparse(const Lattice &lat, bool vertical, int n_r, unsigned long long *acc,
                               hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t st);
+
+// Batched measurement: the E/M reduction and the sparse-set correlation
+// kernels of many lattices of one model in one launch each.  Lattice k of a
+// launch is items[ids[k]]; its counters start at items[.].acc and are laid
+// out as for one lattice: kEmCounters E/M counters, then 2 n_r horizontal,
+// then 2 n_r vertical.  Grid: x walks one lattice's units (blocks past a
+// smaller lattice's units do nothing), y runs over the lattices.
+struct MeasItem {
+    Lattice lat;
+    unsigned long long *acc;
+};
+// Blocks that the single-lattice launch would use for this lattice.
+uint32_t measure_em_blocks(const Lattice &lat);
+hipError_t launch_measure_em_batch(int model, const MeasItem *items, const uint32_t *ids, uint32_t n,
+                                   uint32_t blocks, hipStream_t st);
+// Kind of the sparse-set kernel for one axis of a lattice (lattices of one
+// kind share a launch), and its blocks as in the single-lattice launch.
+int corr_sparse_kind(const Lattice &lat, bool vertical);
+uint32_t corr_sparse_blocks(const Lattice &lat, bool vertical);
+hipError_t launch_corr_sparse_batch(int kind, bool vertical, const MeasItem *items, const uint32_t *ids, uint32_t n,
+                                    uint32_t blocks, int n_r, hipStream_t st);
 // Equilibrium study (paper App. B): one Swendsen-Wang step at sweep index t
 // with the integer bond rule (thr, always), labels = L * L uint32 scratch;
 // and the row / column sums of the spin field (row[L], col[L]; col zeroed by

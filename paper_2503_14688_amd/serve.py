@@ -48,7 +48,7 @@ class GpuBackend:
     as long as the set of active jobs does not change.
 
     The batch is created with a schedule that covers the shortest remaining
-    job, so consecutive epochs of the same jobs replay its captured graph
+    job, so consecutive epochs of the same jobs replay its captured graphs
     without rebuilding anything; a job joining or leaving (or the schedule
     running out) makes the next epoch build a new batch whose replicas continue
     each job's stream (t0 = sweeps done).  The sweep strategy is tuned by the

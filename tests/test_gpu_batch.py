@@ -188,6 +188,27 @@ def test_batch_measure_all_fast_kernels_and_reuse(gpu):
     b.close()
 
 
+def test_batch_measure_all_large_rows(gpu):
+    """The batched measurement launches (one per kernel kind for all
+    replicas) on rows of whole 1024-word segments (L = 65536: the run-per-lane
+    horizontal kernel) next to shorter rows, both models, with the sparse
+    set up to r = 1024: every replica's sums equal its own spin_measure."""
+    reps = [dict(model=m, L=L, seed=workloads.seed_for(7000 + 10 * m + k), J=1.0, Delta=0.0, schedule=m)
+            for m in (0, 1) for k, L in enumerate((1 << 16, 4096, 2048))]
+    n = 2
+    T = np.stack([np.full(n, workloads.TC_ISING), np.full(n, workloads.TC_BC)])
+    b = gpu.Batch(reps, T).init_random()
+    b.run(n)
+    r = workloads.r_sparse(2048)
+    got = b.measure_all(r)
+    for k in range(len(reps)):
+        one = b.measure(k, r)
+        for key in ("t", "sum_s", "sum_s2", "bond"):
+            assert got[k][key] == one[key], (k, key)
+        assert np.array_equal(got[k]["Sx"], one["Sx"]) and np.array_equal(got[k]["Sy"], one["Sy"]), k
+    b.close()
+
+
 def test_borrowed_handles_cannot_advance(gpu):
     """Only spin_batch_run advances a replica: sweeping, cluster-updating or
     re-timing a borrowed handle is refused, so no sweep index is reused."""
@@ -228,6 +249,34 @@ def test_graph_replays_match_direct_runs(gpu):
         assert g.info()["t"] == d.info()["t"] == n * (q + 1)
     for k, rep in enumerate(reps):
         assert np.array_equal(g.spins(k), oracle_run(rep, T[rep["schedule"]], n * runs)), k
+    g.close()
+    d.close()
+
+
+def test_runs_of_any_length_replay_power_of_two_graphs(gpu):
+    """A run of n sweeps replays the captured runs of 2^k sweeps (k <= 8)
+    that n decomposes into, capturing only those not yet captured: runs of
+    lengths 1, 3, 300 (256 + 32 + 8 + 4), 2 and 259 in a row, with eager
+    measurements between them, equal direct launches of the same steps and,
+    at the end, the oracle."""
+    reps = [rep for rep in mixed_replicas() if rep["L"] <= 128]
+    lengths = [1, 3, 300, 2, 259]
+    total = sum(lengths)
+    T = schedules(total)
+    g = gpu.Batch(reps, T).init_random()
+    d = gpu.Batch(reps, T).init_random()
+    done = 0
+    for n in lengths:
+        g.run(n)
+        d.run(n, gpu.BATCH_DIRECT | gpu.BATCH_VARIANT(g.info()["variant"]))
+        g.measure_all([1, 2])
+        d.sync()
+        done += n
+        for k in range(len(reps)):
+            assert np.array_equal(g.spins(k), d.spins(k)), (n, k)
+        assert g.info()["t"] == d.info()["t"] == done
+    for k, rep in enumerate(reps):
+        assert np.array_equal(g.spins(k), oracle_run(rep, T[rep["schedule"]], total)), k
     g.close()
     d.close()
 
