@@ -312,9 +312,13 @@ int spin_batch_replica(spin_batch *b, uint32_t k, spin_handle **out);
  * handle (paper Eqs. 2-3 and App. C): out[k] for replica k, Sx[k * n_r + q]
  * and Sy[k * n_r + q] for separation r[q] (caller-owned host arrays of n and
  * n * n_r entries; Sx, Sy may be NULL when n_r == 0).  Every r[q] must lie in
- * 0 < r < L of every replica.  The kernels of all replicas are queued on the
- * batch's stream into one counter buffer (allocated at the first call, kept
- * by the batch), copied back once; synchronises the batch's stream once. */
+ * 0 < r < L of every replica, and a batch holds at most 65535 replicas for
+ * this call (-EINVAL beyond).  Each reduction and correlation kernel runs
+ * once for all replicas of a model (and kernel kind) when r is a prefix of
+ * the sparse set; replicas whose rows the sparse vertical kernel cannot take,
+ * and every replica for other r, get the general kernels one by one.  All
+ * sums land in one counter buffer (allocated at the first call, kept by the
+ * batch), copied back once; synchronises the batch's stream once. */
 int spin_batch_measure(spin_batch *b, const uint32_t *r, uint32_t n_r, spin_meas *out, int64_t *Sx,
                        int64_t *Sy);
 
