@@ -38,18 +38,18 @@ SWEEP_SOURCES = ["paper_2503_14688_amd/csrc/kernels.hip", "paper_2503_14688_amd/
                  "paper_2503_14688_amd/csrc/device.hpp", "paper_2503_14688_amd/csrc/kernels.hpp"]
 MEASURED_TRAFFIC = {
     # (workload, sweep strategy): bytes per launch
-    ("ising_L1048576_tc", 2): 223.04e9,
-    ("bc_L262144_t16937", 0): 28.47e9,
-    ("bc_L262144_t16937", 1): 27.37e9,
+    ("ising_L1048576_tc", 2): 225.22e9,
+    ("bc_L262144_t16937", 0): 28.53e9,
+    ("bc_L262144_t16937", 1): 27.25e9,
 }
-MEASURED_WITH = "381bc5c53787f9e9"
+MEASURED_WITH = "cbe525478358cd34"
 # (workload, sweep strategy): wave instructions per 64 words of a colour plane
 # (SQ_INSTS_VALU, SQ_INSTS_SALU) and the clock (GHz, GRBM_GUI_ACTIVE over the
 # dispatch) from the same counter pass
 MEASURED_ISSUE = {
-    ("ising_L1048576_tc", 2): (125.7, 86.3, 2.11),
-    ("bc_L262144_t16937", 0): (248.3, 219.6, 2.28),
-    ("bc_L262144_t16937", 1): (240.8, 196.8, 2.15),
+    ("ising_L1048576_tc", 2): (125.8, 84.9, 2.05),
+    ("bc_L262144_t16937", 0): (248.3, 219.6, 2.23),
+    ("bc_L262144_t16937", 1): (233.2, 170.8, 2.08),
 }
 
 
