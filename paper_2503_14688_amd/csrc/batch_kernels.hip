@@ -24,14 +24,21 @@ union BatchList {
     std::conditional_t<kGenList, BcList<kBcGroups, bc_list_cap(VB), variant_rows(VB)>, char> gen;
 };
 
-// Batches of one model (ensembles, protocol-2 batches) are compiled for
-// eight wavefronts per SIMD: there it measured 4-6% faster, with no register
-// spills; the both-model kernel of the tuned mix would spill and measured no
-// faster, so it keeps the compiler's own target.
+// Occupancy target: batches of one model (ensembles, protocol-2 batches)
+// are compiled for eight wavefronts per SIMD, where it measured 4-6% faster
+// with no register spills; the both-model kernel of the mix would spill at
+// eight and takes seven (72 registers instead of 73, no spills, 1.3% faster
+// on the 512-replica mix); batches with the 13-group Blume-Capel path keep
+// the compiler's own target.
 template <int MODELS>
 constexpr int batch_waves()
 {
-    return MODELS == kBatchIsing || MODELS == kBatchBc ? 8 : 1;
+    if constexpr (MODELS == kBatchIsing || MODELS == kBatchBc)
+        return 8;
+    else if constexpr (MODELS == (kBatchIsing | kBatchBc))
+        return 7;
+    else
+        return 1;
 }
 
 // Batched half-sweep: one launch advances colour c of every replica.  The
