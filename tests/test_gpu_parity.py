@@ -296,6 +296,38 @@ def test_blume_capel_uniform_row_tiles_all_strategies(gpu):
         lat.close()
 
 
+@pytest.mark.parametrize("J,Delta,T", [(1.0, 0.5, 1.5), (1.3, -0.9, 2.6)])
+def test_blume_capel_general_delta_all_strategies(gpu, J, Delta, T):
+    """Blume-Capel at Delta != 0 takes the 13-group test (no merged groups, no
+    plane-pattern branch): every sweep strategy, with the fused measurement,
+    gives the oracle's lattice and sums at L = 512 (rows of 8 words), and the
+    tuned one does at L = 4096 (rows of 64 words) over 16 sweeps."""
+    L, seed = 512, 4321
+    Ts = np.full(6, T)
+    s = oracle.init(1, L, seed)
+    oracle.sweep(1, s, seed, J, Delta, 0, Ts)
+    want = oracle.measure(s, [])
+    for v in range(5):
+        lat = make(gpu, 1, L, seed, J, Delta)
+        lat.variant = v
+        lat.sweep(Ts, fuse_measure=True)
+        assert np.array_equal(lat.spins(), s), v
+        got = lat.measure()
+        assert (got["bond"], got["sum_s"], got["sum_s2"]) == (want["bond"], want["sum_s"], want["sum_s2"]), v
+        lat.close()
+    L = 4096
+    r = workloads.r_sparse(L)
+    Ts = np.full(16, T)
+    lat = make(gpu, 1, L, seed, J, Delta)
+    lat.variant = lat.tune(T)
+    s = oracle.init(1, L, seed)
+    lat.sweep(Ts, fuse_measure=True)
+    oracle.sweep(1, s, seed, J, Delta, 0, Ts)
+    assert np.array_equal(lat.spins(), s)
+    compare_measure(lat.measure(r), L, J, Delta, s, r)
+    lat.close()
+
+
 def test_ising_L4096_check_run(gpu):
     """The bit-exact check lattice of the large Ising workload: 2^12 x 2^12, 64 sweeps."""
     w = workloads.ISING_CHECK
