@@ -328,6 +328,27 @@ def test_blume_capel_general_delta_all_strategies(gpu, J, Delta, T):
     lat.close()
 
 
+@pytest.mark.parametrize("model", [0, 1])
+def test_ragged_rows_all_strategies(gpu, model):
+    """L = 4160: rows of 65 words (not a multiple of 64, so the general tile
+    path with its bounds tests) and a last tile of 8-row groups that is only
+    partly filled; every strategy gives the oracle's lattice after 4 sweeps
+    at T_c, and the fused sums equal the oracle's."""
+    L, seed = 4160, 2718
+    T = np.full(4, workloads.TC_ISING if model == 0 else workloads.TC_BC)
+    s = oracle.init(model, L, seed)
+    oracle.sweep(model, s, seed, 1.0, 0.0, 0, T)
+    want = oracle.measure(s, [])
+    for v in range(5):
+        lat = make(gpu, model, L, seed)
+        lat.variant = v
+        lat.sweep(T, fuse_measure=True)
+        assert np.array_equal(lat.spins(), s), v
+        got = lat.measure()
+        assert (got["bond"], got["sum_s"], got["sum_s2"]) == (want["bond"], want["sum_s"], want["sum_s2"]), v
+        lat.close()
+
+
 def test_ising_L4096_check_run(gpu):
     """The bit-exact check lattice of the large Ising workload: 2^12 x 2^12, 64 sweeps."""
     w = workloads.ISING_CHECK
