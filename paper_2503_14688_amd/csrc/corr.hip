@@ -20,6 +20,10 @@
 // 16-byte LDS loads of neighbouring lanes never share a bank, the four
 // separation groups take turns at loading the rows four chunks ahead, and
 // one barrier per 256-row chunk suffices.
+//
+// A batch of lattices is measured by one launch per kernel kind: grid y
+// picks the lattice, grid x walks its tiles or strips as in the launch for
+// one lattice.
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -355,8 +359,9 @@ __global__ __launch_bounds__(kBlock) void k_corr_x_runs(Lattice lat, int n_r, un
     corr_x_runs<MODEL>(lat, n_r, acc);
 }
 
-// Lattice ids[blockIdx.y] of a batch (its horizontal counters follow the
-// E/M counters).
+// The same sums for lattice items[ids[blockIdx.y]] of a batch, one launch
+// for all lattices of one kind (its horizontal counters follow its E/M
+// counters; blocks past a smaller lattice's tiles find none).
 template <int MODEL, bool RUNS>
 __global__ __launch_bounds__(kBlock) void k_corr_x_batch(const MeasItem *__restrict__ items,
                                                          const uint32_t *__restrict__ ids, int n_r)
@@ -621,8 +626,9 @@ __global__ __launch_bounds__(kYThreads) void k_corr_y_ring(Lattice lat, int n_r,
     corr_y_ring<MODEL>(lat, n_r, RING, acc);
 }
 
-// Lattice ids[blockIdx.y] of a batch (its vertical counters follow the E/M
-// and horizontal counters).
+// The same sums for lattice items[ids[blockIdx.y]] of a batch, one launch
+// for all lattices of one model (its vertical counters follow its E/M and
+// horizontal counters; blocks past a smaller lattice's strips find none).
 template <int MODEL>
 __global__ __launch_bounds__(kYThreads) void k_corr_y_batch(const MeasItem *__restrict__ items,
                                                             const uint32_t *__restrict__ ids, int n_r, uint32_t RING)
