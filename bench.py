@@ -411,11 +411,10 @@ def single_lattice(wl, steps, warmup, variant=-1):
 
 def run_equilibrium(args):
     """Equilibrium Blume-Capel at Delta = 0 (App. B): independent runs per L
-    (each on its own stream) of EMCS = 10 Metropolis sweeps + 1 Swendsen-Wang
-    step at T_c^BC, U4 and xi_2/L from the Fourier moments, and the
-    reweighted crossings beta_{L,U}, beta_{L,xi2/L} with jackknife errors."""
+    (one batch per L) of EMCS = 10 Metropolis sweeps + 1 Swendsen-Wang step at
+    T_c^BC, U4 and xi_2/L from the Fourier moments, and the reweighted
+    crossings beta_{L,U}, beta_{L,xi2/L} with jackknife errors."""
     import torch
-    import paper_2503_14688_amd as spin
     from paper_2503_14688_amd import equilibrium, workloads
     wl = dict(workloads.EQUILIBRIUM_BC)
     if getattr(args, "equilibrium_sizes", None):
@@ -431,16 +430,12 @@ def run_equilibrium(args):
            "T_c_paper": "1.6935583(5)", "sizes": {}}
     est = {"beta_U": ([], []), "beta_xi": ([], [])}
     for L in wl["sizes"]:
-        streams = [torch.cuda.Stream() for _ in range(wl["runs"])]
-        lats = [spin.Lattice(wl["model"], L, workloads.seed_for(wl["seed0"] + 1000 * k + L), stream=st).init_random()
-                for k, st in enumerate(streams)]
+        seeds = [workloads.seed_for(wl["seed0"] + 1000 * k + L) for k in range(wl["runs"])]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        runs = equilibrium.emcs_runs(lats, T, wl["n_emcs"], wl["every"], wl["n_therm"])
+        runs = equilibrium.emcs_batch(wl["model"], L, seeds, T, wl["n_emcs"], wl["every"], wl["n_therm"])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        for lat in lats:
-            lat.close()
         c = equilibrium.crossings(runs, L, beta0)
         j = equilibrium.jackknife_observables(runs, L, beta0)
         n_emcs = wl["runs"] * (wl["n_therm"] + wl["n_emcs"])

@@ -322,6 +322,23 @@ int spin_batch_replica(spin_batch *b, uint32_t k, spin_handle **out);
 int spin_batch_measure(spin_batch *b, const uint32_t *r, uint32_t n_r, spin_meas *out, int64_t *Sx,
                        int64_t *Sy);
 
+/* One Swendsen-Wang step on every replica (paper App. B; as spin_sw on each
+ * replica alone): replica k's step runs at its schedule's temperature for
+ * the batch's current step and at sweep index t0 + t, then the batch moves
+ * on by one step, like a one-sweep spin_batch_run, so runs and steps can
+ * alternate (the elementary Monte Carlo step of the equilibrium study: n
+ * sweeps, then one cluster step).  Every replica must have L <= 32768
+ * (-EINVAL otherwise); cluster labels (L * L uint32 per replica) are
+ * allocated at the first call and kept by the replica's handle. */
+int spin_batch_sw(spin_batch *b);
+
+/* Fourier moments of every replica's current state, as spin_measure_fourier
+ * on each replica alone (without the row and column sums): out[k] for
+ * replica k (caller-owned host array of n entries).  One counter buffer for
+ * all replicas (allocated at the first call, kept by the batch), one copy
+ * back, one synchronisation of the batch's stream. */
+int spin_batch_measure_fourier(spin_batch *b, spin_fourier *out);
+
 /* Replica count, sweeps this batch has run, batched strategy in use (-1 before
  * the first run) and tiles per half-sweep; any output may be NULL. */
 int spin_batch_info(const spin_batch *b, uint32_t *n_replicas, uint64_t *t, int *variant, uint64_t *tiles);

@@ -69,8 +69,8 @@ EXPORTS = ["spin_lattice_bytes", "spin_create", "spin_init_random", "spin_sweep"
            "spin_get_t", "spin_threshold_table", "spin_schedule_fill", "spin_destroy",
            "spin_set_variant", "spin_get_variant", "spin_tune", "spin_sw", "spin_measure_fourier",
            "spin_last_error", "spin_batch_create", "spin_batch_init_random", "spin_batch_run",
-           "spin_batch_sync", "spin_batch_replica", "spin_batch_measure", "spin_batch_info",
-           "spin_batch_destroy"]
+           "spin_batch_sync", "spin_batch_replica", "spin_batch_measure", "spin_batch_sw",
+           "spin_batch_measure_fourier", "spin_batch_info", "spin_batch_destroy"]
 
 
 def load_library():
@@ -123,6 +123,8 @@ def load_library():
         "spin_batch_sync": (ctypes.c_int, [vp]),
         "spin_batch_replica": (ctypes.c_int, [vp, ctypes.c_uint32, ctypes.POINTER(vp)]),
         "spin_batch_measure": (ctypes.c_int, [vp, u32p, ctypes.c_uint32, ctypes.POINTER(spin_meas), i64p, i64p]),
+        "spin_batch_sw": (ctypes.c_int, [vp]),
+        "spin_batch_measure_fourier": (ctypes.c_int, [vp, ctypes.POINTER(spin_fourier)]),
         "spin_batch_info": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64),
                                            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_uint64)]),
         "spin_batch_destroy": (ctypes.c_int, [vp]),
@@ -322,6 +324,19 @@ def spin_batch_measure(b, n, r=()):
              "Sx": Sx[k], "Sy": Sy[k]} for k, o in enumerate(out)]
 
 
+def spin_batch_sw(b):
+    _check(load_library().spin_batch_sw(b))
+
+
+def spin_batch_measure_fourier(b, n):
+    """Per-replica Fourier moments: list of dicts as spin_measure_fourier
+    returns, without the row and column sums."""
+    out = (spin_fourier * n)()
+    _check(load_library().spin_batch_measure_fourier(b, out))
+    return [{"t": o.t, "sum_s": o.sum_s, "sum_s2": o.sum_s2, "bond": o.bond, "e": o.e,
+             "k1": complex(o.re_k1, o.im_k1), "k2": complex(o.re_k2, o.im_k2)} for o in out]
+
+
 def spin_batch_replica(b, k):
     h = ctypes.c_void_p()
     _check(load_library().spin_batch_replica(b, k, ctypes.byref(h)))
@@ -456,6 +471,13 @@ class Batch:
 
     def measure_all(self, r=()):
         return spin_batch_measure(self.b, len(self.reps), r)
+
+    def sw(self):
+        """One Swendsen-Wang step on every replica (one schedule step)."""
+        spin_batch_sw(self.b)
+
+    def fourier_all(self):
+        return spin_batch_measure_fourier(self.b, len(self.reps))
 
     def info(self):
         return spin_batch_info(self.b)

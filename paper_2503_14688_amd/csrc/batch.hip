@@ -32,6 +32,8 @@ struct spin_batch {
     std::vector<spin_handle *> reps;
     std::vector<uint32_t> table_of;     // replica -> threshold table id
     std::vector<uint64_t> t0;           // replica -> sweep index of schedule step 0
+    std::vector<uint32_t> sched_of;     // replica -> schedule
+    std::vector<double> T;              // the schedules (n_sched x n_steps), for the Swendsen-Wang rule
     uint32_t n_tables = 0, n_steps = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -49,6 +51,8 @@ struct spin_batch {
     uint32_t *d_ids = nullptr;             // replica lists of the batched measurement launches
     std::vector<spin::MeasItem> h_items;   // host sides of the two (kept until the copy is done)
     std::vector<uint32_t> h_ids;
+    long long *d_fourier = nullptr;      // per replica: 4 E/M counters, L row sums, L column sums
+    size_t fourier_len = 0;              // entries
     uint32_t *d_step = nullptr;          // schedule step on the device (= t between runs)
     // captured runs of 2^k sweeps, k = 0 .. kGraphLog, for strategy graph_variant
     hipGraph_t graph[kGraphLog + 1] = {};
@@ -100,6 +104,8 @@ void release(spin_batch *b)
         (void)hipFree(b->d_items);
     if (b->d_ids)
         (void)hipFree(b->d_ids);
+    if (b->d_fourier)
+        (void)hipFree(b->d_fourier);
     if (b->d_step)
         (void)hipFree(b->d_step);
     for (spin_handle *h : b->reps)
@@ -296,6 +302,7 @@ int spin_batch_create(uint32_t n, const spin_replica_desc *descs, uint32_t n_sch
     if (!b)
         return fail(-ENOMEM, "out of host memory");
     b->n_steps = n_steps;
+    b->T.assign(T, T + (size_t)n_sched * n_steps);
     if (hip_stream) {
         b->stream = (hipStream_t)hip_stream;
     } else {
@@ -332,6 +339,7 @@ int spin_batch_create(uint32_t n, const spin_replica_desc *descs, uint32_t n_sch
             b->models |= spin::kBatchBcGeneral;
         b->reps.push_back(h);
         b->t0.push_back(d.t0);
+        b->sched_of.push_back(d.schedule);
         auto key = std::make_tuple(d.model, d.J, d.Delta, d.schedule);
         auto it = ids.find(key);
         if (it == ids.end())
@@ -455,6 +463,89 @@ int spin_batch_run(spin_batch *b, uint32_t n, uint32_t flags)
     for (size_t r = 0; r < b->reps.size(); ++r) {
         b->reps[r]->t = b->t0[r] + b->t;
         b->reps[r]->em_valid = false;
+    }
+    return 0;
+}
+
+int spin_batch_sw(spin_batch *b)
+{
+    if (!b)
+        return fail(-EINVAL, "NULL batch");
+    if (b->t + 1 > b->n_steps)
+        return fail(-EINVAL, "schedule has %u steps, %llu done, 1 asked", b->n_steps, (unsigned long long)b->t);
+    for (spin_handle *h : b->reps)
+        if (h->L > kMaxSwL)
+            return fail(-EINVAL, "Swendsen-Wang steps need L <= %u (got %u)", kMaxSwL, h->L);
+    for (spin_handle *h : b->reps)
+        if (!h->d_labels) {
+            hipError_t e = hipMalloc(&h->d_labels, (size_t)h->L * h->L * sizeof(uint32_t));
+            if (e != hipSuccess) {
+                h->d_labels = nullptr;
+                return fail(-ENOMEM, "cluster labels for L = %u: %s", h->L, hipGetErrorString(e));
+            }
+        }
+    // each replica's step at its own schedule's temperature and sweep index,
+    // as spin_sw on the replica alone; then the device step counter moves on
+    // with the host's, so later runs read the next schedule step
+    for (size_t r = 0; r < b->reps.size(); ++r) {
+        spin_handle *h = b->reps[r];
+        const double Tk = b->T[(size_t)b->sched_of[r] * b->n_steps + b->t];
+        uint32_t thr;
+        const bool always = sw_rule(h->J, Tk, &thr);
+        HIP_TRY(spin::launch_sw_step(h->lat, (uint32_t)(b->t0[r] + b->t), thr, always, h->d_labels, b->stream),
+                "Swendsen-Wang launch");
+    }
+    HIP_TRY(spin::launch_advance_step(b->d_step, 1, b->stream), "step counter launch");
+    b->t += 1;
+    for (size_t r = 0; r < b->reps.size(); ++r) {
+        b->reps[r]->t = b->t0[r] + b->t;
+        b->reps[r]->em_valid = false;
+    }
+    return 0;
+}
+
+int spin_batch_measure_fourier(spin_batch *b, spin_fourier *out)
+{
+    if (!b || !out)
+        return fail(-EINVAL, "NULL batch or result pointer");
+    const size_t n = b->reps.size();
+    std::vector<size_t> off(n + 1, 0);
+    for (size_t r = 0; r < n; ++r)
+        off[r + 1] = off[r] + spin::kEmCounters + 2 * (size_t)b->reps[r]->L;
+    const size_t total = off[n];
+    if (total > b->fourier_len) {
+        HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+        if (b->d_fourier)
+            (void)hipFree(b->d_fourier);
+        b->fourier_len = 0;
+        hipError_t e = hipMalloc(&b->d_fourier, total * sizeof(long long));
+        if (e != hipSuccess) {
+            b->d_fourier = nullptr;
+            return fail(-ENOMEM, "row and column sums: %s", hipGetErrorString(e));
+        }
+        b->fourier_len = total;
+    }
+    // one fill, the E/M reduction and the line sums of every replica, one
+    // copy, one synchronisation
+    HIP_TRY(spin::launch_fill_u64((unsigned long long *)b->d_fourier, total, 0ull, b->stream), "fill kernel launch");
+    for (size_t r = 0; r < n; ++r) {
+        long long *base = b->d_fourier + off[r];
+        const uint32_t L = b->reps[r]->L;
+        HIP_TRY(spin::launch_measure_em(b->reps[r]->lat, (unsigned long long *)base, b->stream),
+                "measure kernel launch");
+        HIP_TRY(spin::launch_line_sums(b->reps[r]->lat, base + spin::kEmCounters, base + spin::kEmCounters + L,
+                                       b->stream),
+                "line-sum kernel launch");
+    }
+    std::vector<long long> host(total);
+    HIP_TRY(hipMemcpyAsync(host.data(), b->d_fourier, total * sizeof(long long), hipMemcpyDeviceToHost, b->stream),
+            "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    for (size_t r = 0; r < n; ++r) {
+        unsigned long long acc[spin::kEmCounters];
+        for (int q = 0; q < spin::kEmCounters; ++q)
+            acc[q] = (unsigned long long)host[off[r] + q];
+        finish_fourier(b->reps[r], acc, host.data() + off[r] + spin::kEmCounters, out + r);
     }
     return 0;
 }

@@ -14,10 +14,7 @@
 
 using namespace spin_host;
 
-namespace {
-
-// Largest L the cluster forest supports: labels are 32-bit site indices.
-constexpr uint32_t kMaxSwL = 32768;
+namespace spin_host {
 
 // Bond rule of the Swendsen-Wang step: a bond between equal non-zero spins is
 // active with probability p = 1 - exp(-2J/T); in integers, u < floor(2^32 p),
@@ -33,7 +30,35 @@ bool sw_rule(double J, double T, uint32_t *thr)
     return false;
 }
 
-} // namespace
+void finish_fourier(const spin_handle *h, const unsigned long long *acc, const long long *lines, spin_fourier *out)
+{
+    const uint32_t L = h->L;
+    const double N = (double)L * (double)L;
+    out->t = h->t;
+    out->sum_s = (int64_t)acc[0] - 2 * (int64_t)acc[1];
+    out->sum_s2 = (int64_t)acc[0];
+    out->bond = (int64_t)acc[2] - 2 * (int64_t)acc[3];
+    out->e = (-h->J * (double)out->bond + h->Delta * (double)out->sum_s2) / N;
+    // M(k) = sum_x exp(i k.x) s_x for k = (2 pi / L, 0) and (0, 2 pi / L):
+    // the phase depends on one coordinate only, so M(k) is the discrete
+    // Fourier sum of the row (resp. column) sums
+    const double two_pi = 2.0 * std::acos(-1.0);
+    double re1 = 0.0, im1 = 0.0, re2 = 0.0, im2 = 0.0;
+    for (uint32_t q = 0; q < L; ++q) {
+        const double a = two_pi * (double)q / (double)L;
+        const double ca = std::cos(a), sa = std::sin(a);
+        re1 += (double)lines[q] * ca;
+        im1 += (double)lines[q] * sa;
+        re2 += (double)lines[L + q] * ca;
+        im2 += (double)lines[L + q] * sa;
+    }
+    out->re_k1 = re1;
+    out->im_k1 = im1;
+    out->re_k2 = re2;
+    out->im_k2 = im2;
+}
+
+} // namespace spin_host
 
 extern "C" {
 
@@ -103,29 +128,7 @@ int spin_measure_fourier(spin_handle *h, spin_fourier *out, int64_t *row_sums, i
             "hipMemcpyAsync");
     HIP_TRY(hipMemcpyAsync(acc, h->d_acc, sizeof acc, hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync");
     HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-    const double N = (double)L * (double)L;
-    out->t = h->t;
-    out->sum_s = (int64_t)acc[0] - 2 * (int64_t)acc[1];
-    out->sum_s2 = (int64_t)acc[0];
-    out->bond = (int64_t)acc[2] - 2 * (int64_t)acc[3];
-    out->e = (-h->J * (double)out->bond + h->Delta * (double)out->sum_s2) / N;
-    // M(k) = sum_x exp(i k.x) s_x for k = (2 pi / L, 0) and (0, 2 pi / L):
-    // the phase depends on one coordinate only, so M(k) is the discrete
-    // Fourier sum of the row (resp. column) sums
-    const double two_pi = 2.0 * std::acos(-1.0);
-    double re1 = 0.0, im1 = 0.0, re2 = 0.0, im2 = 0.0;
-    for (uint32_t q = 0; q < L; ++q) {
-        const double a = two_pi * (double)q / (double)L;
-        const double ca = std::cos(a), sa = std::sin(a);
-        re1 += (double)lines[q] * ca;
-        im1 += (double)lines[q] * sa;
-        re2 += (double)lines[L + q] * ca;
-        im2 += (double)lines[L + q] * sa;
-    }
-    out->re_k1 = re1;
-    out->im_k1 = im1;
-    out->re_k2 = re2;
-    out->im_k2 = im2;
+    finish_fourier(h, acc, lines.data(), out);
     for (uint32_t q = 0; row_sums && q < L; ++q)
         row_sums[q] = lines[q];
     for (uint32_t q = 0; col_sums && q < L; ++q)

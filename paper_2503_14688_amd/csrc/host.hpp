@@ -51,6 +51,14 @@ int queue_correlations(const spin::Lattice &lat, const uint32_t *r, uint32_t n_r
                        hipStream_t st);
 void finish_measure(const spin_handle *h, const unsigned long long *acc, const uint32_t *r, uint32_t n_r,
                     spin_meas *out, int64_t *Sx, int64_t *Sy, double *C_hat);
+// Swendsen-Wang steps (paper App. B): largest L of the cluster forest (labels
+// are 32-bit site indices), the integer bond rule at bath temperature T
+// (returns true when every bond between equal non-zero spins is active,
+// else sets *thr), and the Fourier moments from copied-back E/M counters and
+// row / column sums (lines[0..L) rows, lines[L..2L) columns).
+constexpr uint32_t kMaxSwL = 32768;
+bool sw_rule(double J, double T, uint32_t *thr);
+void finish_fourier(const spin_handle *h, const unsigned long long *acc, const long long *lines, spin_fourier *out);
 // Coherence length I2 / I1 (trapezoid rule up to the first non-positive
 // C-hat) from the correlation sums; writes C-hat(r_q) when C_hat is not NULL.
 double xi_from_sums(const uint32_t *r, const int64_t *Sx, const int64_t *Sy, uint32_t n_r, double N, double C0,

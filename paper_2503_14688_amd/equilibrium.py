@@ -73,6 +73,34 @@ def emcs_runs(lats, T, n_emcs, every=1, n_therm=0, n_metropolis=EMCS_METROPOLIS)
     return [{k: np.array(v) for k, v in o.items()} for o in out]
 
 
+def emcs_batch(model, L, seeds, T, n_emcs, every=1, n_therm=0, n_metropolis=EMCS_METROPOLIS, J=1.0, Delta=0.0):
+    """emcs_run for independent lattices of one size (one per seed, from the
+    T = infinity start) held in one batch: each elementary step is one batched
+    run of n_metropolis sweeps and one batched Swendsen-Wang step, each
+    measurement one batched Fourier call.  Lattice k draws the random numbers
+    it would draw alone (seed k, sweep index from 0), so the samples equal
+    emcs_run's on the same lattices.  Returns one sample dict per lattice."""
+    from . import Batch
+    n_steps = (n_therm + n_emcs) * (n_metropolis + 1)
+    Ts = np.full((1, max(n_steps, 1)), float(T))
+    reps = [dict(model=model, L=L, seed=int(s), J=J, Delta=Delta, schedule=0) for s in seeds]
+    b = Batch(reps, Ts).init_random()
+    out = [{"H": [], "M0": [], "Mk2": []} for _ in seeds]
+    try:
+        for k in range(n_therm + n_emcs):
+            if n_metropolis > 0:
+                b.run(n_metropolis)
+            b.sw()
+            if k >= n_therm and (k - n_therm + 1) % every == 0:
+                for o, f in zip(out, b.fourier_all()):
+                    o["H"].append(-J * float(f["bond"]) + Delta * float(f["sum_s2"]))
+                    o["M0"].append(float(f["sum_s"]))
+                    o["Mk2"].append(0.5 * (abs(f["k1"]) ** 2 + abs(f["k2"]) ** 2))
+    finally:
+        b.close()
+    return [{k: np.array(v) for k, v in o.items()} for o in out]
+
+
 def jackknife_observables(runs, L, beta0, beta=None):
     """U4 and xi_2 / L at beta (default beta0) with jackknife errors over runs."""
     full = observables(concat(runs), L, beta0, beta)

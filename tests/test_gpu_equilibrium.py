@@ -105,3 +105,47 @@ def test_swendsen_wang_arguments(gpu):
         gpu.spin_sw(h, [2.0])
     assert ei.value.code == -22
     gpu.spin_destroy(h)
+
+
+def test_batched_elementary_steps_match_oracle_and_solo_runs(gpu):
+    """spin_batch_sw and spin_batch_measure_fourier: a batch of both models
+    and three sizes, with per-replica schedules and couplings, alternating
+    runs of Metropolis sweeps with batched Swendsen-Wang steps, gives every
+    replica the oracle's configuration after each step and the Fourier
+    moments of its own spin_measure_fourier; equilibrium.emcs_batch gives the
+    samples of emcs_run on the same lattices alone."""
+    from paper_2503_14688_amd import equilibrium
+    reps = [dict(model=m, L=L, seed=5100 + 10 * m + L, J=J, Delta=0.0, schedule=m)
+            for m, L, J in ((0, 64, 1.0), (1, 128, 1.2), (1, 320, 1.0), (0, 192, 0.9))]
+    n_metropolis, n_steps = 3, 4
+    total = n_steps * (n_metropolis + 1)
+    T = np.stack([np.linspace(3.0, TC[0], total), np.full(total, TC[1])])
+    b = gpu.Batch(reps, T).init_random()
+    states = [oracle.init(r["model"], r["L"], r["seed"]) for r in reps]
+    t = 0
+    for k in range(n_steps):
+        b.run(n_metropolis)
+        b.sw()
+        for r, s in zip(reps, states):
+            Tr = T[r["schedule"]]
+            oracle.sweep(r["model"], s, r["seed"], r["J"], 0.0, t, Tr[t:t + n_metropolis])
+            oracle.sw(r["model"], s, r["seed"], r["J"], t + n_metropolis, Tr[t + n_metropolis:t + n_metropolis + 1])
+        t += n_metropolis + 1
+        got = b.fourier_all()
+        for q, (r, s) in enumerate(zip(reps, states)):
+            assert np.array_equal(b.spins(q), s), (k, q)
+            one = gpu.spin_measure_fourier(b.replica(q), r["L"])
+            for key in ("t", "sum_s", "sum_s2", "bond", "e", "k1", "k2"):
+                assert got[q][key] == one[key], (k, q, key)
+            assert got[q]["t"] == t
+    with pytest.raises(gpu.SpinError):
+        b.sw()  # the schedule is used up
+    b.close()
+    seeds = [7001, 7002, 7003]
+    batched = equilibrium.emcs_batch(1, 64, seeds, TC[1], 6, every=2, n_therm=2, n_metropolis=4)
+    for seed, got in zip(seeds, batched):
+        lat = gpu.Lattice(1, 64, seed).init_random()
+        want = equilibrium.emcs_run(lat, TC[1], 6, every=2, n_therm=2, n_metropolis=4)
+        lat.close()
+        for key in ("H", "M0", "Mk2"):
+            assert np.array_equal(got[key], want[key]), (seed, key)
