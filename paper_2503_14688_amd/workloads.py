@@ -98,8 +98,8 @@ ENSEMBLE_BC = dict(name="ensemble_bc_L4096_tc", model=1, L=1 << 12, replicas=64,
 # Swendsen-Wang step, 40 EMCS of thermalisation (the paper's equilibration
 # time at L = 4096), then 2000 EMCS measured after every step (the paper: L up
 # to 4096, 100 runs of 4 x 10^5 EMCS each).
-EQUILIBRIUM_BC = dict(name="equilibrium_bc_tc", model=1, sizes=(64, 128, 256, 512, 1024, 2048), runs=16, n_therm=40,
-                      n_emcs=2000, every=1, T=TC_BC, seed0=3000)
+EQUILIBRIUM_BC = dict(name="equilibrium_bc_tc", model=1, sizes=(64, 128, 256, 512, 1024, 2048, 4096), runs=16,
+                      n_therm=40, n_emcs=2000, every=1, T=TC_BC, seed0=3000)
 
 
 def batched_replicas(n=512, sizes=(256, 512, 1024, 2048), taus=(64.0, 256.0, 1024.0)):
