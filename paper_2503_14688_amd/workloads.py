@@ -81,14 +81,15 @@ PROTOCOL2_BC = dict(name="protocol2_bc_L16384", model=1, L=1 << 14, T1=1.24, T2=
                     t_after=4096, t_limit=65536, replicas=4, seed=SEED_BASE + 7)
 
 
-# Ensemble of direct quenches for the analysis of App. C and D: 64 Ising
+# Ensemble of direct quenches for the analysis of App. C and D: 128 Ising
 # replicas of L = 4096 at T_c measured on a grid of two times per octave up to
-# t = 8192 (xi grows to about 40, L / xi > 100), z fitted from t = 256 on.
-ENSEMBLE_ISING = dict(name="ensemble_ising_L4096_tc", model=0, L=1 << 12, replicas=64, T=TC_ISING,
+# t = 8192 (xi = I2 / I1 grows to about 170, L / xi about 24), z fitted from
+# t = 256 on.
+ENSEMBLE_ISING = dict(name="ensemble_ising_L4096_tc", model=0, L=1 << 12, replicas=128, T=TC_ISING,
                       t_max=8192, per_octave=2, fit_from=256, seed0=1000)
 # The same for Blume-Capel (Delta = 0) at its T_c (Table I): the paper's
 # universality claim is one z for both models.
-ENSEMBLE_BC = dict(name="ensemble_bc_L4096_tc", model=1, L=1 << 12, replicas=64, T=TC_BC,
+ENSEMBLE_BC = dict(name="ensemble_bc_L4096_tc", model=1, L=1 << 12, replicas=128, T=TC_BC,
                    t_max=8192, per_octave=2, fit_from=256, seed0=2000)
 
 
