@@ -43,6 +43,17 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_batch_calls_reject_null_batches():
+    """The batch entry points check their arguments before any HIP call."""
+    lib = spin.load_library()
+    out = (spin.spin_fourier * 1)()
+    assert lib.spin_batch_sw(None) == -22
+    assert lib.spin_batch_measure_fourier(None, out) == -22
+    assert lib.spin_batch_run(None, 1, 0) == -22
+    assert lib.spin_batch_measure(None, None, 0, None, None, None) == -22
+    assert "NULL" in spin.spin_last_error()
+
+
 def test_lattice_bytes_and_validation():
     assert spin.spin_lattice_bytes(spin.ISING, 64) == 64 * 64 // 8
     assert spin.spin_lattice_bytes(spin.BLUME_CAPEL, 64) == 64 * 64 // 4
